@@ -1,0 +1,297 @@
+"""ctypes wrapper of the FP64 CPU oracle (``lbm_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark.  The product package never imports it.
+
+The oracle follows the paper's Sec. 3 (Eqs. 1-5, collision and streaming),
+Sec. 3.1 (Eqs. 6-8, immersed boundary), Alg. 1 (bounce-back) and Alg. 2 (step
+order); see the header of ``lbm_oracle.c`` for the readings it takes where the
+paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbm_oracle.c")
+LIB = os.path.join(HERE, "liblbm_oracle.so")
+
+PERIODIC, NOSLIP, FREESLIP, INLET, OUTFLOW = 0, 1, 2, 3, 4
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP, IEEE FP64, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", SRC, "-o", tmp, "-lm"]
+        )
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        dp, ip, fp = C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_float)
+        vp = C.c_void_p
+        L.orc_lattice.argtypes = [ip, dp, ip, ip]
+        L.orc_central_matrix.argtypes = [dp, dp]
+        L.orc_combination_matrix.argtypes = [dp]
+        L.orc_basis_matrix.argtypes = [dp, dp]
+        L.orc_inverse.argtypes = [dp, dp, C.c_int]
+        L.orc_inverse.restype = C.c_int
+        L.orc_equilibrium.argtypes = [C.c_double, dp, dp]
+        L.orc_collide.argtypes = [dp, dp, C.c_double, C.c_double, dp, dp]
+        L.orc_collide.restype = C.c_int
+        L.orc_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, ip, dp, C.c_double, dp, dp, C.c_int]
+        L.orc_create.restype = vp
+        L.orc_destroy.argtypes = [vp]
+        L.orc_num_cells.argtypes = [vp]
+        L.orc_num_cells.restype = C.c_int64
+        L.orc_set_state.argtypes = [vp, dp]
+        L.orc_get_state.argtypes = [vp, dp]
+        L.orc_set_inlet_profile.argtypes = [vp, dp]
+        L.orc_init_equilibrium.argtypes = [vp, dp, dp]
+        L.orc_check_markers.argtypes = [vp, C.c_int64, fp]
+        L.orc_check_markers.restype = C.c_int64
+        L.orc_set_markers.argtypes = [vp, C.c_int64, fp, dp, dp, dp]
+        L.orc_set_markers.restype = C.c_int
+        L.orc_step.argtypes = [vp, C.c_int]
+        L.orc_step.restype = C.c_int
+        L.orc_macros.argtypes = [vp, dp, dp]
+        L.orc_last_force.argtypes = [vp, dp]
+        L.orc_ib_force.argtypes = [vp, dp, dp]
+        L.orc_get_force_field.argtypes = [vp, dp]
+        L.orc_conserved.argtypes = [vp, dp]
+        L.orc_marker_key.argtypes = [vp, fp]
+        L.orc_marker_key.restype = C.c_uint64
+        L.orc_maps.argtypes = [vp, C.POINTER(C.c_uint8), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.orc_set_scalar.argtypes = [vp, dp, C.c_int]
+        L.orc_get_scalar.argtypes = [vp, dp]
+        L.orc_num_threads.restype = C.c_int
+        L.orc_stream.argtypes = [vp, dp]
+        L.orc_ib_interp.argtypes = [vp, dp, dp, dp]
+        L.orc_ib_spread.argtypes = [vp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# single-cell and matrix helpers
+# --------------------------------------------------------------------------
+
+def lattice():
+    """(c[27,3], w[27], opp[27], moment exponents[27,3])."""
+    c = np.zeros((27, 3), np.int32)
+    w = np.zeros(27)
+    opp = np.zeros(27, np.int32)
+    e = np.zeros((27, 3), np.int32)
+    lib().orc_lattice(_p(c, C.c_int), _p(w, C.c_double), _p(opp, C.c_int), _p(e, C.c_int))
+    return c, w, opp, e
+
+
+def central_matrix(u) -> np.ndarray:
+    T = np.zeros((27, 27))
+    lib().orc_central_matrix(_p(_d(u), C.c_double), _p(T, C.c_double))
+    return T
+
+
+def combination_matrix() -> np.ndarray:
+    Cm = np.zeros((27, 27))
+    lib().orc_combination_matrix(_p(Cm, C.c_double))
+    return Cm
+
+
+def basis_matrix(u) -> np.ndarray:
+    M = np.zeros((27, 27))
+    lib().orc_basis_matrix(_p(_d(u), C.c_double), _p(M, C.c_double))
+    return M
+
+
+def inverse(A) -> np.ndarray:
+    A = _d(A)
+    n = A.shape[0]
+    R = np.zeros_like(A)
+    rc = lib().orc_inverse(_p(A, C.c_double), _p(R, C.c_double), n)
+    if rc != 0:
+        raise np.linalg.LinAlgError("singular")
+    return R
+
+
+def equilibrium(rho, u) -> np.ndarray:
+    out = np.zeros(27)
+    lib().orc_equilibrium(float(rho), _p(_d(u), C.c_double), _p(out, C.c_double))
+    return out
+
+
+def collide(fs, F=(0.0, 0.0, 0.0), s_nu=1.0, s_b=1.0, s_high=(1.0, 1.0, 1.0, 1.0)) -> np.ndarray:
+    out = np.zeros(27)
+    rc = lib().orc_collide(
+        _p(_d(fs), C.c_double), _p(_d(F), C.c_double), float(s_nu), float(s_b),
+        _p(_d(s_high), C.c_double), _p(out, C.c_double)
+    )
+    if rc != 0:
+        raise np.linalg.LinAlgError("singular moment matrix")
+    return out
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# --------------------------------------------------------------------------
+# whole-domain simulation
+# --------------------------------------------------------------------------
+
+class OracleSim:
+    """FP64 reference simulation on an nx x ny x nz grid.
+
+    Arrays follow the library's conventions: a scalar field is [nz, ny, nx]
+    (x fastest), a vector field [3, nz, ny, nx], populations [27, nz, ny, nx].
+    ``faces`` is (-x, +x, -y, +y, -z, +z) with PERIODIC/NOSLIP/FREESLIP/INLET/
+    OUTFLOW codes.
+    """
+
+    def __init__(self, nx, ny, nz, nu, faces=(0,) * 6, u_in=(0.0, 0.0, 0.0), s_bulk=1.0,
+                 s_high=(1.0, 1.0, 1.0, 1.0), body=(0.0, 0.0, 0.0), scalar=False):
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+        fc = np.ascontiguousarray(np.asarray(faces, dtype=np.int32))
+        self._h = lib().orc_create(nx, ny, nz, float(nu), _p(fc, C.c_int), _p(_d(u_in), C.c_double),
+                                   float(s_bulk), _p(_d(s_high), C.c_double), _p(_d(body), C.c_double),
+                                   1 if scalar else 0)
+        if not self._h:
+            raise ValueError("invalid oracle parameters")
+        self.n_markers = 0
+
+    def close(self):
+        if self._h:
+            lib().orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # state ------------------------------------------------------------
+    def init_equilibrium(self, rho, u):
+        lib().orc_init_equilibrium(self._h, _p(_d(rho).ravel(), C.c_double), _p(_d(u).ravel(), C.c_double))
+
+    def set_state(self, f):
+        f = _d(f).reshape(27, self.N)
+        lib().orc_set_state(self._h, _p(f, C.c_double))
+
+    def get_state(self) -> np.ndarray:
+        f = np.zeros((27,) + self.shape)
+        lib().orc_get_state(self._h, _p(f, C.c_double))
+        return f
+
+    def set_inlet_profile(self, prof):
+        if prof is None:
+            lib().orc_set_inlet_profile(self._h, None)
+        else:
+            lib().orc_set_inlet_profile(self._h, _p(_d(prof).ravel(), C.c_double))
+
+    def set_markers(self, xyz, ub=None, area=None, gain=None):
+        xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float32))
+        n = xyz.shape[1]
+        ub = None if ub is None else _d(ub)
+        area = None if area is None else _d(area)
+        gain = None if gain is None else _d(gain)
+        rc = lib().orc_set_markers(
+            self._h, n, _p(xyz, C.c_float),
+            None if ub is None else _p(ub, C.c_double),
+            None if area is None else _p(area, C.c_double),
+            None if gain is None else _p(gain, C.c_double))
+        if rc != 0:
+            raise ValueError("marker outside the domain")
+        self.n_markers = n
+        self._xyz = xyz
+
+    def step(self, n=1):
+        if lib().orc_step(self._h, int(n)) != 0:
+            raise FloatingPointError("singular moment matrix (non-finite state)")
+
+    def macros(self):
+        rho = np.zeros(self.shape)
+        u = np.zeros((3,) + self.shape)
+        lib().orc_macros(self._h, _p(rho, C.c_double), _p(u, C.c_double))
+        return rho, u
+
+    def last_force(self):
+        out = np.zeros(3)
+        lib().orc_last_force(self._h, _p(out, C.c_double))
+        return out
+
+    def ib_force(self, per_marker=False):
+        out = np.zeros(3)
+        gs = np.zeros((3, max(self.n_markers, 1)))
+        lib().orc_ib_force(self._h, _p(out, C.c_double), _p(gs, C.c_double) if per_marker else None)
+        return (out, gs[:, : self.n_markers]) if per_marker else out
+
+    def force_field(self):
+        g = np.zeros((3,) + self.shape)
+        lib().orc_get_force_field(self._h, _p(g, C.c_double))
+        return g
+
+    def conserved(self):
+        out = np.zeros(4)
+        lib().orc_conserved(self._h, _p(out, C.c_double))
+        return out
+
+    def maps(self):
+        n = self.n_markers
+        flags = np.zeros(self.shape, np.uint8)
+        cell = np.zeros(max(n, 1), np.int32)
+        perm = np.zeros(max(n, 1), np.int32)
+        lib().orc_maps(self._h, _p(flags, C.c_uint8), _p(cell, C.c_int32), _p(perm, C.c_int32))
+        return flags, cell[:n], perm[:n]
+
+    def marker_key(self, p) -> int:
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        return int(lib().orc_marker_key(self._h, _p(p, C.c_float)))
+
+    def stream(self) -> np.ndarray:
+        out = np.zeros((27,) + self.shape)
+        lib().orc_stream(self._h, _p(out, C.c_double))
+        return out
+
+    def ib_interp(self, rho, u) -> np.ndarray:
+        G = np.zeros((3, max(self.n_markers, 1)))
+        lib().orc_ib_interp(self._h, _p(_d(rho).ravel(), C.c_double), _p(_d(u).ravel(), C.c_double),
+                            _p(G, C.c_double))
+        return G[:, : self.n_markers]
+
+    def ib_spread(self, G) -> np.ndarray:
+        g = np.zeros((3,) + self.shape)
+        Gd = _d(G).reshape(3, -1) if self.n_markers else np.zeros((3, 1))
+        lib().orc_ib_spread(self._h, _p(np.ascontiguousarray(Gd), C.c_double), _p(g, C.c_double))
+        return g
+
+    def set_scalar(self, s, inlet_height):
+        lib().orc_set_scalar(self._h, _p(_d(s).ravel(), C.c_double), int(inlet_height))
+
+    def get_scalar(self):
+        s = np.zeros(self.shape)
+        lib().orc_get_scalar(self._h, _p(s, C.c_double))
+        return s
