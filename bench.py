@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the D3Q27 central-moment MRT step on one MI355X.
+
+Workload (the headline configuration): decaying turbulence on a 256^3 periodic
+grid, no solids, FP32 populations, nu = 1e-4, equilibrium initialisation from
+a seeded E(k) ~ k^-5/3 solenoidal field (rms u = 0.04, rho = 1 +- 1e-3).  A
+"step" is one full time step of the method (pull streaming, macroscopic
+values, central-moment collision, store) over all cells.
+
+Prints one JSON line: MLUPS, the roofline of the fused kernel (algorithmic
+bytes per launch / measured launch time, against 8 TB/s), the FP64 CPU oracle
+timed on a bounded slab of the same field, and extra objects for the 16-bit
+storage forms and the immersed-sphere workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (D3Q27 ACM-MRT+IBM), % HBM roofline; FP16-store vs FP32 at stated error"
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "k_fused_turbulence256_f32_counters.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2101_11856_amd", "csrc", f) for f in ("lbm_step.hip", "lbm_internal.hpp")]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def timed_steps(solver, steps, warmup):
+    import torch
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(solver.stream)
+    solver.step(steps)
+    e1.record(solver.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def turbulence_solver(n, storage, rho, u):
+    from paper_2101_11856_amd import lbm
+    s = lbm.Solver(n, n, n, 1e-4, storage=storage)
+    s.init_equilibrium(rho, u)
+    return s
+
+
+def cpu_baseline(rho, u, n, budget_s=12.0):
+    """FP64 oracle on a 256 x 256 x 16 periodic slab of the same field."""
+    import numpy as np
+
+    from oracle import oracle as O
+    nz = 16
+    S = O.OracleSim(n, n, nz, 1e-4)
+    S.init_equilibrium(rho[:nz].astype(np.float64), u[:, :nz].astype(np.float64))
+    steps, t0 = 0, time.perf_counter()
+    while steps < 8:
+        S.step(1)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    cells = n * n * nz
+    return {"value": round(cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} step(s) of the FP64 oracle on a {n}x{n}x{nz} periodic slab of the same "
+                      f"turbulence field ({cells} cells, {dt:.1f} s)"}
+
+
+def sphere_workload(steps, warmup):
+    import torch
+
+    from paper_2101_11856_amd import lbm, synth
+    nx, ny, nz = 512, 128, 128
+    s = lbm.Solver(nx, ny, nz, 5e-5, faces=(lbm.INLET, lbm.OUTFLOW, 0, 0, 0, 0), u_in=(0.05, 0.0, 0.0))
+    rho, u = synth.uniform(nx, ny, nz, (0.05, 0.0, 0.0))
+    s.init_equilibrium(rho, u)
+    xyz, ub, area, gain = synth.sphere_scene()
+    s.set_solids(xyz, ub, area, gain)
+    t = timed_steps(s, steps, warmup)
+    F = s.ib_force()
+    out = {"workload": "flow past an immersed sphere 512x128x128, inlet/outflow, 13000 sphere + 200000 "
+                       "random samples, FP32", "value": round(nx * ny * nz * steps / t / 1e6, 1),
+           "unit": "MLUPS", "ms_per_step": round(1e3 * t / steps, 4), "samples": int(xyz.shape[1]),
+           "band_nodes": None, "drag_x": float(-F[0])}
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="grid edge of the turbulence workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 16-bit and sphere runs")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 "
+                                   "(the multi-GPU slab decomposition is a design, not a measured path)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2101_11856_amd import synth
+
+    n = args.n
+    log(f"generating turbulence field {n}^3")
+    rho, u = synth.turbulence(n)
+    cells = n ** 3
+
+    log("fp32 run")
+    s = turbulence_solver(n, "f32", rho, u)
+    c0 = s.conserved()
+    torch.cuda.synchronize()
+    t = timed_steps(s, args.steps, args.warmup)
+    c1 = s.conserved()
+    _, u32 = s.macros()
+    u32 = u32.cpu().numpy()
+    mlups = cells * args.steps / t / 1e6
+    t_launch = t / args.steps          # only the fused kernel runs in this workload
+    bytes_launch = 27 * 2 * 4 * cells  # algorithmic: read + write 27 FP32 per cell
+    achieved = bytes_launch / t_launch / 1e9
+    traffic = measured_traffic()
+    result = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_launch, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"decaying turbulence {n}^3 periodic, no solids, FP32 populations, nu=1e-4",
+                   "cells": cells, "nu": 1e-4, "storage": "f32"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / t_launch / 1e9, 1),
+                     "kernel": "k_fused<f32>", "algorithmic_bytes_per_launch": bytes_launch},
+        "mass_drift_rel": float(abs(c1[0] - c0[0]) / c0[0]),
+    }
+    del s
+    torch.cuda.empty_cache()
+
+    if not args.no_extras:
+        for storage in ("f16", "bf16"):
+            log(f"{storage} run")
+            s = turbulence_solver(n, storage, rho, u)
+            t16 = timed_steps(s, args.steps, args.warmup)
+            _, u16 = s.macros()
+            u16 = u16.cpu().numpy()
+            m16 = cells * args.steps / t16 / 1e6
+            err = float(np.linalg.norm(u16 - u32) / np.linalg.norm(u32))
+            result[f"{storage}_storage"] = {
+                "value": round(m16, 1), "unit": "MLUPS", "ratio_vs_f32": round(m16 / mlups, 3),
+                "ms_per_step": round(1e3 * t16 / args.steps, 4),
+                "achieved_GBs": round(27 * 2 * 2 * cells / (t16 / args.steps) / 1e9, 1),
+                "vel_rel_l2_vs_f32_gpu": err,
+                "error_note": f"after {args.warmup + args.steps} steps of this workload, against the FP32 run "
+                              "(which matches the FP64 oracle to <= 1e-5)"}
+            del s
+            torch.cuda.empty_cache()
+        log("sphere run")
+        result["ib_sphere"] = sphere_workload(min(args.steps, 100), min(args.warmup, 10))
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(rho, u, n)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

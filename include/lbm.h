@@ -1,0 +1,184 @@
+/*
+ * lbm.h -- C-ABI of liblbm: one time step of the D3Q27 central-moment MRT
+ * lattice Boltzmann method with immersed-boundary coupling, on one MI355X
+ * (gfx950), after Chen, Li, Fan, Liu, "GPU Optimization for High-Quality
+ * Kinetic Fluid Simulation" (arXiv:2101.11856).
+ *
+ * General rules
+ *  - Every function has C linkage, returns an lbm_status (except
+ *    lbm_destroy / lbm_last_error) and never throws or aborts.
+ *  - The library never allocates device memory: the caller passes one device
+ *    workspace at create time (size from lbm_workspace_size) and one for the
+ *    solid samples (size from lbm_solids_ws_size).  Both stay owned by the
+ *    caller and must outlive the context.
+ *  - All work is enqueued on the caller's HIP stream given to lbm_create (or
+ *    lbm_set_stream).  Calls marked "sync" wait for that stream; all others are
+ *    asynchronous and return after enqueueing.
+ *  - Arguments are validated on the host before any launch; a failure returns
+ *    LBM_E_INVAL and leaves the state unchanged.  HIP errors map to LBM_E_HIP.
+ *    lbm_last_error() gives a message for the last failure on a context.
+ *  - "real" below is float, except double when storage == LBM_F64.
+ *  - Grid arrays are [nz][ny][nx] with x fastest (linear index
+ *    x + nx*(y + ny*z)); vector fields are [3][nz][ny][nx]; population arrays
+ *    are [27][nz][ny][nx].  N = nx*ny*nz must stay below 2^31.
+ *
+ * Lattice (Sec. 3, Eq. 1 and Fig. 1; the values come from the paper's
+ * supplementary document, which is not available, so they are this
+ * library's reading): c_i in {-1,0,1}^3; index 0 rest, 1-6 faces, 7-18 edges
+ * (xy, xz, yz planes), 19-26 corners; inside each group the sign patterns run
+ * with x fastest, so c_1 = (1,0,0), c_2 = (-1,0,0), ..., c_26 = (-1,-1,-1).
+ * This order reproduces the coefficients printed in the paper's expression
+ * for Omega_26 (Sec. 4.4.2) and in Table 2.  Weights 8/27, 2/27, 1/54, 1/216.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_INVAL = 1,       /* bad argument, detected before any launch     */
+    LBM_E_NOMEM = 2,       /* a caller workspace is too small              */
+    LBM_E_HIP = 3,         /* a HIP runtime call failed                    */
+    LBM_E_NONFINITE = 4,   /* a check found NaN/Inf in the state           */
+    LBM_E_STATE = 5,       /* call made in the wrong order                 */
+    LBM_E_UNSUPPORTED = 6  /* valid request this build does not implement  */
+} lbm_status;
+
+/* Domain faces, order -x, +x, -y, +y, -z, +z (Sec. 4.3.3: the domain boundary
+ * is treated by bounce-back, Alg. 1).  Readings of the face types:
+ *  NOSLIP   halfway bounce-back: f*_i(x) = f_opp(i)(x)           (Alg. 1)
+ *  INLET    (face -x only) bounce-back with the wall velocity of the inflow:
+ *           f*_i(x) = f_opp(i)(x) + 2 w_i rho_w (c_i . u_in(y,z)) / cs^2,
+ *           rho_w = 1, cs^2 = 1/3
+ *  OUTFLOW  (face +x only) zero gradient: the streamed value is copied from
+ *           the node one step inward
+ *  FREESLIP specular reflection of the normal velocity component
+ *  PERIODIC wrap-around; must be set on both faces of an axis.
+ * Where the source x - c_i crosses several faces the rule of the highest
+ * precedence applies: NOSLIP > INLET > OUTFLOW > FREESLIP > PERIODIC. */
+typedef enum { LBM_PERIODIC = 0, LBM_NOSLIP = 1, LBM_FREESLIP = 2, LBM_INLET = 3, LBM_OUTFLOW = 4 } lbm_face;
+
+/* Population storage.  Every 16-bit and 32-bit form stores the deviation
+ * d_i = f_i - w_i from the lattice weights; arithmetic is FP32 except LBM_F64
+ * (FP64 storage and arithmetic).  16-bit forms round to nearest even. */
+typedef enum { LBM_F32 = 0, LBM_F16DEV = 1, LBM_BF16DEV = 2, LBM_F64 = 3 } lbm_storage;
+
+typedef struct {
+    int32_t nx, ny, nz;          /* nodes per axis (>= 1; >= 2 on an axis with a non-periodic face) */
+    double nu;                   /* lattice kinematic viscosity > 0; shear rate s_nu = 1/(3 nu + 1/2) (Sec. 3) */
+    int32_t face[6];             /* lbm_face codes, -x,+x,-y,+y,-z,+z */
+    double u_in[3];              /* uniform inlet velocity used when inlet_profile == NULL */
+    const void *inlet_profile;   /* optional device real[3][nz][ny], caller-owned; read at every step */
+    double body_force[3];        /* uniform body force density added to every node */
+    double s_bulk;               /* relaxation rate of the second-order trace (bulk), 0 < s < 2 */
+    double s_high[4];            /* rates of central moments of order 3, 4, 5, 6 (0 < s < 2) */
+    int32_t storage;             /* lbm_storage */
+    int32_t passive_scalar;      /* 0/1: advect a passive scalar (first-order upwind) */
+    int32_t scalar_inlet_height; /* scalar held at 1 on inlet nodes with y < this height */
+} lbm_params;
+
+/* Fill *p with defaults: periodic faces, s_bulk = s_high = 1, FP32, no scalar. */
+lbm_status lbm_default_params(lbm_params *p, int32_t nx, int32_t ny, int32_t nz, double nu);
+
+/* Device bytes the caller must provide to lbm_create for these parameters. */
+lbm_status lbm_workspace_size(const lbm_params *p, size_t *bytes);
+
+/* Create a context on the current HIP device.  `workspace` is device memory of
+ * at least lbm_workspace_size() bytes (256-byte aligned), `hip_stream` a
+ * hipStream_t (NULL = default stream).  The state is zero (f = w) until
+ * lbm_init_equilibrium / lbm_set_populations / lbm_restore.  Sync. */
+lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out);
+
+lbm_status lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
+
+/* Equilibrium initialisation f_i = f_eq_i(rho, u) (product form
+ * rho prod_a phi_{c_ia}(u_a), phi_0 = 2/3 - u^2, phi_{+-1} = (1/3 +- u + u^2)/2,
+ * whose central moments are those of the Maxwellian).  rho: device real[N],
+ * u: device real[3][N].  Async. */
+lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const void *rho, const void *u);
+
+/* Full populations f_i (not deviations) in and out, device real[27][N]. Async. */
+lbm_status lbm_set_populations(lbm_ctx *ctx, const void *f);
+lbm_status lbm_get_populations(lbm_ctx *ctx, void *f);
+
+/* Passive scalar field in and out, device float[N] (needs passive_scalar). Async. */
+lbm_status lbm_set_scalar(lbm_ctx *ctx, const float *s);
+lbm_status lbm_get_scalar(lbm_ctx *ctx, float *s);
+
+/* Device bytes of the sample workspace for n samples (lbm_set_solids). */
+lbm_status lbm_solids_ws_size(const lbm_ctx *ctx, int64_t n, size_t *bytes);
+
+/* Immersed solid samples (Sec. 3.1).  xyz: device float[3][n] positions in
+ * lattice units (node k at coordinate k); ub: device float[3][n] boundary
+ * velocity u_b; area: device float[n] area weight a_s of Eq. (8) (NULL = 1);
+ * gain: device float[n] penalty gain gamma_s of Eq. (7) (NULL = 1).
+ * A sample must lie in [0, n_a) on a periodic axis and in [0, n_a - 1) on an
+ * axis with non-periodic faces (its 2x2x2 stencil stays inside).  The samples
+ * are sorted (Sec. 4.2.2: l^3 blocks, l = 4, in x-y-z order, Morton order of
+ * the position inside a block, original index on ties) and copied into
+ * marker_ws (device, caller-owned, lbm_solids_ws_size bytes), so the inputs
+ * may be freed afterwards.  n = 0 removes all samples.  Sync. */
+lbm_status lbm_set_solids(lbm_ctx *ctx, int64_t n, const float *xyz, const float *ub, const float *area,
+                          const float *gain, void *marker_ws, size_t marker_ws_bytes);
+
+/* Advance n time steps (Alg. 2): for each step, pull streaming with the face
+ * rules (Eq. 3), rho and u (Eq. 2), then if samples are set: interpolation
+ * and penalty force (Eqs. 6-7) and spreading by per-sample scattering with
+ * atomic additions (Eq. 8, Sec. 4.3.2), then the central-moment collision with
+ * force (Eqs. 4-5), stored to the other population buffer.  Async. */
+lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps);
+
+/* rho and u = j / rho (Eq. 2) of the populations that the next step would
+ * stream in (a read-only pull of the current state).  rho: device real[N],
+ * u: device real[3][N].  Async. */
+lbm_status lbm_macros(lbm_ctx *ctx, void *rho, void *u);
+
+/* FP64 totals of the stored populations: out = {sum f, sum c_x f, sum c_y f,
+ * sum c_z f} (Eq. 1 conserves them).  Returns LBM_E_NONFINITE if any stored
+ * value is NaN or Inf.  Sync. */
+lbm_status lbm_conserved(lbm_ctx *ctx, double out[4]);
+
+/* FP64 total sum_s a_s g_s of the penalty force applied in the last step
+ * (force on the fluid; drag on the solid is its negative).  Sync. */
+lbm_status lbm_ib_force(lbm_ctx *ctx, double out[3]);
+
+/* FP64 total penalty force that the next step would apply, evaluated from the
+ * current state without changing it.  Sync. */
+lbm_status lbm_ib_force_eval(lbm_ctx *ctx, double out[3]);
+
+/* Integer maps of the samples (bit-exact).  flags: device uint8[N], bit 0 =
+ * node inside some sample's 2x2x2 stencil (receives force), bit 1 = base cell
+ * floor(x_s) of some sample; marker_cell: device int32[n], linear index of the
+ * base cell of sample s (input order); marker_perm: device int32[n], input
+ * index of the k-th sample in sorted order.  Any pointer may be NULL.  Async. */
+lbm_status lbm_solid_maps(lbm_ctx *ctx, uint8_t *flags, int32_t *marker_cell, int32_t *marker_perm);
+
+/* Snapshot of the state (populations and scalar) into / from device memory of
+ * lbm_state_bytes() bytes, caller-owned.  Async. */
+lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
+lbm_status lbm_checkpoint(lbm_ctx *ctx, void *dst);
+lbm_status lbm_restore(lbm_ctx *ctx, const void *src);
+
+/* Release the host-side context (the workspaces stay with the caller). */
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Message of the last failure on ctx (or of the last failed lbm_create when
+ * ctx is NULL); never NULL. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Library version string. */
+const char *lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,422 @@
+// lbm_api.hip -- the extern "C" surface of liblbm (include/lbm.h): argument
+// validation on the host, carving of the caller's workspaces, and launch
+// sequencing on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "lbm_ctx.hpp"
+
+using namespace lbm;
+
+namespace {
+
+std::string g_create_err = "no error";
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+lbm_status fail(lbm_ctx *c, lbm_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_create_err = msg;
+    return s;
+}
+
+lbm_status hip_fail(lbm_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, LBM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool valid_rate(double s) { return std::isfinite(s) && s > 0.0 && s < 2.0; }
+
+// extra elements between population planes (spreads the 27 concurrent
+// streams over HBM channels); tunable for measurements
+int64_t plane_skew()
+{
+    const char *e = std::getenv("LBM_PLANE_SKEW");
+    if (!e) return 0;
+    const long v = std::strtol(e, nullptr, 10);
+    return v > 0 ? (int64_t)v : 0;
+}
+
+lbm_status validate(const lbm_params *p, std::string &err)
+{
+    if (!p) return err = "params is NULL", LBM_E_INVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return err = "grid dimensions must be >= 1", LBM_E_INVAL;
+    const int64_t nxp = (int64_t)align_up((size_t)p->nx, 32);
+    if ((int64_t)p->nx * p->ny * p->nz >= (1ll << 31) || nxp * p->ny * p->nz >= (1ll << 31))
+        return err = "grid too large: nx*ny*nz (padded) must stay below 2^31", LBM_E_INVAL;
+    if (!std::isfinite(p->nu) || !(p->nu > 0.0)) return err = "nu must be finite and > 0", LBM_E_INVAL;
+    const int n[3] = {p->nx, p->ny, p->nz};
+    for (int f = 0; f < 6; ++f)
+        if (p->face[f] < LBM_PERIODIC || p->face[f] > LBM_OUTFLOW) return err = "unknown face code", LBM_E_INVAL;
+    for (int a = 0; a < 3; ++a) {
+        const bool pm = p->face[2 * a] == LBM_PERIODIC, pp = p->face[2 * a + 1] == LBM_PERIODIC;
+        if (pm != pp) return err = "PERIODIC must be set on both faces of an axis", LBM_E_INVAL;
+        if (!pm && n[a] < 2) return err = "an axis with non-periodic faces needs >= 2 nodes", LBM_E_INVAL;
+    }
+    for (int f = 0; f < 6; ++f) {
+        if (p->face[f] == LBM_INLET && f != 0) return err = "INLET is supported on face -x only", LBM_E_INVAL;
+        if (p->face[f] == LBM_OUTFLOW && f != 1) return err = "OUTFLOW is supported on face +x only", LBM_E_INVAL;
+    }
+    if (!valid_rate(p->s_bulk)) return err = "s_bulk must be in (0, 2)", LBM_E_INVAL;
+    for (int k = 0; k < 4; ++k)
+        if (!valid_rate(p->s_high[k])) return err = "s_high rates must be in (0, 2)", LBM_E_INVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->u_in[a]) || !std::isfinite(p->body_force[a]))
+            return err = "u_in and body_force must be finite", LBM_E_INVAL;
+    if (p->storage < LBM_F32 || p->storage > LBM_F64) return err = "unknown storage", LBM_E_INVAL;
+    if (p->passive_scalar != 0 && p->passive_scalar != 1) return err = "passive_scalar must be 0 or 1", LBM_E_INVAL;
+    return LBM_OK;
+}
+
+struct Layout {
+    int nxp, ntx;
+    int64_t plane, W, rows;
+    size_t esize, rsize;
+    size_t offA, offB, offSA, offSB, offPart, offOut, offFt, offFe, offFlag, total;
+    int red_blocks;
+};
+
+Layout layout(const lbm_params *p)
+{
+    Layout L{};
+    L.nxp = (int)align_up((size_t)p->nx, 32);
+    L.ntx = (p->nx + SEG - 1) / SEG;
+    L.rows = (int64_t)p->ny * p->nz;
+    L.W = (int64_t)L.ntx * L.rows;
+    L.plane = (int64_t)align_up((size_t)(L.rows * L.nxp), 64) + plane_skew();
+    L.esize = p->storage == LBM_F32 ? 4 : p->storage == LBM_F64 ? 8 : 2;
+    L.rsize = p->storage == LBM_F64 ? 8 : 4;
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    L.red_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 255) / 256));
+    const size_t fbytes = align_up((size_t)Q * L.plane * L.esize, ALIGN);
+    const size_t sbytes = p->passive_scalar ? align_up((size_t)L.rows * L.nxp * 4, ALIGN) : 0;
+    size_t o = 0;
+    L.offA = o;
+    o += fbytes;
+    L.offB = o;
+    o += fbytes;
+    L.offSA = o;
+    o += sbytes;
+    L.offSB = o;
+    o += sbytes;
+    L.offPart = o;
+    o += align_up((size_t)L.red_blocks * 4 * 8, ALIGN);
+    L.offOut = o;
+    o += ALIGN;
+    L.offFt = o;
+    o += ALIGN;
+    L.offFe = o;
+    o += ALIGN;
+    L.offFlag = o;
+    o += ALIGN;
+    L.total = o;
+    return L;
+}
+
+size_t state_bytes(const lbm_ctx *c)
+{
+    size_t b = (size_t)Q * c->g.plane * c->esize;
+    if (c->p.passive_scalar) b += (size_t)c->rows * c->g.nxp * 4;
+    return b;
+}
+
+#define CHECK_CTX(c)                                                             \
+    do {                                                                         \
+        if (!(c)) return fail(nullptr, LBM_E_INVAL, "context is NULL");          \
+    } while (0)
+#define HIP_TRY(c, expr, where)                                                  \
+    do {                                                                         \
+        const hipError_t e_ = (expr);                                            \
+        if (e_ != hipSuccess) return hip_fail((c), e_, (where));                 \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_default_params(lbm_params *p, int32_t nx, int32_t ny, int32_t nz, double nu)
+{
+    if (!p) return fail(nullptr, LBM_E_INVAL, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->nx = nx;
+    p->ny = ny;
+    p->nz = nz;
+    p->nu = nu;
+    p->s_bulk = 1.0;
+    for (int k = 0; k < 4; ++k) p->s_high[k] = 1.0;
+    p->storage = LBM_F32;
+    return LBM_OK;
+}
+
+lbm_status lbm_workspace_size(const lbm_params *p, size_t *bytes)
+{
+    std::string err;
+    const lbm_status s = validate(p, err);
+    if (s != LBM_OK) return fail(nullptr, s, err);
+    if (!bytes) return fail(nullptr, LBM_E_INVAL, "bytes is NULL");
+    *bytes = layout(p).total;
+    return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out)
+{
+    std::string err;
+    lbm_status s = validate(p, err);
+    if (s != LBM_OK) return fail(nullptr, s, err);
+    if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!workspace) return fail(nullptr, LBM_E_INVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % ALIGN)
+        return fail(nullptr, LBM_E_INVAL, "workspace must be 256-byte aligned");
+    const Layout L = layout(p);
+    if (ws_bytes < L.total)
+        return fail(nullptr, LBM_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    c->p = *p;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    hipGetDevice(&c->device);
+    c->g.nx = p->nx;
+    c->g.ny = p->ny;
+    c->g.nz = p->nz;
+    c->g.nxp = L.nxp;
+    c->g.ntx = L.ntx;
+    c->g.plane = L.plane;
+    c->g.W = L.W;
+    for (int f = 0; f < 6; ++f) c->g.face[f] = p->face[f];
+    c->N = (int64_t)p->nx * p->ny * p->nz;
+    c->rows = L.rows;
+    c->esize = L.esize;
+    c->rsize = L.rsize;
+    c->ws = static_cast<char *>(workspace);
+    c->ws_bytes = ws_bytes;
+    c->fA = c->ws + L.offA;
+    c->fB = c->ws + L.offB;
+    if (p->passive_scalar) {
+        c->scA = reinterpret_cast<float *>(c->ws + L.offSA);
+        c->scB = reinterpret_cast<float *>(c->ws + L.offSB);
+    }
+    c->red_part = reinterpret_cast<double *>(c->ws + L.offPart);
+    c->red_out = reinterpret_cast<double *>(c->ws + L.offOut);
+    c->ftot = reinterpret_cast<double *>(c->ws + L.offFt);
+    c->ftot_eval = reinterpret_cast<double *>(c->ws + L.offFe);
+    c->red_flag = reinterpret_cast<int *>(c->ws + L.offFlag);
+    c->red_blocks = L.red_blocks;
+    c->s_nu = 1.0 / (3.0 * p->nu + 0.5);
+    c->s_b = p->s_bulk;
+    for (int k = 0; k < 4; ++k) c->s_h[k] = p->s_high[k];
+    // state f = w (zero deviations), zero scalar and force totals
+    hipError_t e = launch_zero(c, c->ws, L.offPart);
+    if (e == hipSuccess) e = launch_zero(c, c->ws + L.offOut, L.total - L.offOut);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        g_create_err = std::string("lbm_create: ") + hipGetErrorString(e);
+        delete c;
+        return LBM_E_HIP;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_stream(lbm_ctx *c, void *hip_stream)
+{
+    CHECK_CTX(c);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return LBM_OK;
+}
+
+lbm_status lbm_init_equilibrium(lbm_ctx *c, const void *rho, const void *u)
+{
+    CHECK_CTX(c);
+    if (!rho || !u) return fail(c, LBM_E_INVAL, "rho and u must be non-NULL");
+    HIP_TRY(c, launch_init_eq(c, rho, u), "lbm_init_equilibrium");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_ctx *c, const void *f)
+{
+    CHECK_CTX(c);
+    if (!f) return fail(c, LBM_E_INVAL, "f is NULL");
+    HIP_TRY(c, launch_set_pop(c, f), "lbm_set_populations");
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx *c, void *f)
+{
+    CHECK_CTX(c);
+    if (!f) return fail(c, LBM_E_INVAL, "f is NULL");
+    HIP_TRY(c, launch_get_pop(c, f), "lbm_get_populations");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_scalar(lbm_ctx *c, const float *s)
+{
+    CHECK_CTX(c);
+    if (!c->p.passive_scalar) return fail(c, LBM_E_STATE, "context was created without a passive scalar");
+    if (!s) return fail(c, LBM_E_INVAL, "s is NULL");
+    HIP_TRY(c, launch_scalar_io(c, c->scA, s, true), "lbm_set_scalar");
+    return LBM_OK;
+}
+
+lbm_status lbm_get_scalar(lbm_ctx *c, float *s)
+{
+    CHECK_CTX(c);
+    if (!c->p.passive_scalar) return fail(c, LBM_E_STATE, "context was created without a passive scalar");
+    if (!s) return fail(c, LBM_E_INVAL, "s is NULL");
+    HIP_TRY(c, launch_scalar_io(c, s, c->scA, false), "lbm_get_scalar");
+    return LBM_OK;
+}
+
+lbm_status lbm_solids_ws_size(const lbm_ctx *c, int64_t n, size_t *bytes)
+{
+    if (!c) return fail(nullptr, LBM_E_INVAL, "context is NULL");
+    if (n < 0 || n >= (1ll << 31) || !bytes) return fail(const_cast<lbm_ctx *>(c), LBM_E_INVAL, "bad sample count");
+    SolidsLayout L;
+    const hipError_t e = solids_layout(c, n, &L);
+    if (e != hipSuccess) return hip_fail(const_cast<lbm_ctx *>(c), e, "lbm_solids_ws_size");
+    *bytes = L.total;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_solids(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area,
+                          const float *gain, void *marker_ws, size_t marker_ws_bytes)
+{
+    CHECK_CTX(c);
+    if (n < 0 || n >= (1ll << 31)) return fail(c, LBM_E_INVAL, "sample count out of range");
+    if (n == 0) {
+        c->nm = 0;
+        c->nband = 0;
+        return LBM_OK;
+    }
+    if (!xyz) return fail(c, LBM_E_INVAL, "xyz is NULL");
+    if (!marker_ws || reinterpret_cast<uintptr_t>(marker_ws) % ALIGN)
+        return fail(c, LBM_E_INVAL, "marker_ws must be non-NULL and 256-byte aligned");
+    SolidsLayout L;
+    hipError_t e = solids_layout(c, n, &L);
+    if (e != hipSuccess) return hip_fail(c, e, "lbm_set_solids");
+    if (marker_ws_bytes < L.total)
+        return fail(c, LBM_E_NOMEM, "marker workspace too small: need " + std::to_string(L.total) + " bytes");
+    c->nm = 0;
+    c->nband = 0;
+    c->mws = static_cast<char *>(marker_ws);
+    c->mws_bytes = marker_ws_bytes;
+    int bad = 0;
+    e = solids_setup(c, n, xyz, ub, area, gain, &bad);
+    if (e != hipSuccess) return hip_fail(c, e, "lbm_set_solids");
+    if (bad) {
+        return fail(c, LBM_E_INVAL,
+                    std::to_string(bad) +
+                        " sample(s) outside the domain (need [0,n) on periodic axes, [0,n-1) on bounded axes)");
+    }
+    c->nm = n;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int32_t nsteps)
+{
+    CHECK_CTX(c);
+    if (nsteps < 0) return fail(c, LBM_E_INVAL, "nsteps must be >= 0");
+    for (int32_t t = 0; t < nsteps; ++t) {
+        if (c->nm > 0) HIP_TRY(c, launch_band_ib(c, c->ftot), "lbm_step (immersed boundary)");
+        HIP_TRY(c, launch_fused(c), "lbm_step (fused)");
+        std::swap(c->fA, c->fB);
+        std::swap(c->scA, c->scB);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_macros(lbm_ctx *c, void *rho, void *u)
+{
+    CHECK_CTX(c);
+    if (!rho || !u) return fail(c, LBM_E_INVAL, "rho and u must be non-NULL");
+    HIP_TRY(c, launch_macros(c, rho, u), "lbm_macros");
+    return LBM_OK;
+}
+
+lbm_status lbm_conserved(lbm_ctx *c, double out[4])
+{
+    CHECK_CTX(c);
+    if (!out) return fail(c, LBM_E_INVAL, "out is NULL");
+    HIP_TRY(c, launch_conserved(c), "lbm_conserved");
+    int flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(out, c->red_out, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "lbm_conserved");
+    HIP_TRY(c, hipMemcpyAsync(&flag, c->red_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "lbm_conserved");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "lbm_conserved");
+    if (flag) return fail(c, LBM_E_NONFINITE, "non-finite populations in the state");
+    return LBM_OK;
+}
+
+lbm_status lbm_ib_force(lbm_ctx *c, double out[3])
+{
+    CHECK_CTX(c);
+    if (!out) return fail(c, LBM_E_INVAL, "out is NULL");
+    HIP_TRY(c, hipMemcpyAsync(out, c->ftot, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "lbm_ib_force");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "lbm_ib_force");
+    return LBM_OK;
+}
+
+lbm_status lbm_ib_force_eval(lbm_ctx *c, double out[3])
+{
+    CHECK_CTX(c);
+    if (!out) return fail(c, LBM_E_INVAL, "out is NULL");
+    if (c->nm == 0) {
+        out[0] = out[1] = out[2] = 0.0;
+        return LBM_OK;
+    }
+    HIP_TRY(c, launch_band_ib(c, c->ftot_eval), "lbm_ib_force_eval");
+    HIP_TRY(c, hipMemcpyAsync(out, c->ftot_eval, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+            "lbm_ib_force_eval");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "lbm_ib_force_eval");
+    return LBM_OK;
+}
+
+lbm_status lbm_solid_maps(lbm_ctx *c, uint8_t *flags, int32_t *marker_cell, int32_t *marker_perm)
+{
+    CHECK_CTX(c);
+    HIP_TRY(c, launch_solid_maps(c, flags, marker_cell, marker_perm), "lbm_solid_maps");
+    return LBM_OK;
+}
+
+lbm_status lbm_state_bytes(const lbm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return fail(const_cast<lbm_ctx *>(c), LBM_E_INVAL, "NULL argument");
+    *bytes = state_bytes(c);
+    return LBM_OK;
+}
+
+lbm_status lbm_checkpoint(lbm_ctx *c, void *dst)
+{
+    CHECK_CTX(c);
+    if (!dst) return fail(c, LBM_E_INVAL, "dst is NULL");
+    const size_t fb = (size_t)Q * c->g.plane * c->esize;
+    HIP_TRY(c, launch_copy(c, dst, c->fA, fb), "lbm_checkpoint");
+    if (c->p.passive_scalar)
+        HIP_TRY(c, launch_copy(c, static_cast<char *>(dst) + fb, c->scA, (size_t)c->rows * c->g.nxp * 4),
+                "lbm_checkpoint");
+    return LBM_OK;
+}
+
+lbm_status lbm_restore(lbm_ctx *c, const void *src)
+{
+    CHECK_CTX(c);
+    if (!src) return fail(c, LBM_E_INVAL, "src is NULL");
+    const size_t fb = (size_t)Q * c->g.plane * c->esize;
+    HIP_TRY(c, launch_copy(c, c->fA, src, fb), "lbm_restore");
+    if (c->p.passive_scalar)
+        HIP_TRY(c, launch_copy(c, c->scA, static_cast<const char *>(src) + fb, (size_t)c->rows * c->g.nxp * 4),
+                "lbm_restore");
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c) { delete c; }
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+const char *lbm_version(void) { return "liblbm 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// lbm_ctx.hpp -- host-side context of liblbm and the launchers each kernel
+// translation unit provides.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "lbm.h"
+#include "lbm_internal.hpp"
+
+struct lbm_ctx {
+    lbm_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    lbm::Geom g{};
+    int64_t N = 0;         // nx*ny*nz
+    int64_t rows = 0;      // ny*nz
+    size_t esize = 4;      // bytes per stored population
+    size_t rsize = 4;      // bytes of the arithmetic type
+    // caller workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    void *fA = nullptr, *fB = nullptr;  // fA = current state
+    float *scA = nullptr, *scB = nullptr;
+    double *red_part = nullptr;  // [red_blocks][4]
+    int *red_flag = nullptr;     // non-finite count
+    double *red_out = nullptr;   // [4]
+    double *ftot = nullptr;      // [3] IB force of the last step
+    double *ftot_eval = nullptr; // [3] IB force evaluated by lbm_ib_force_eval
+    int red_blocks = 0;
+    // relaxation rates
+    double s_nu = 1, s_b = 1, s_h[4] = {1, 1, 1, 1};
+    // solid samples (marker workspace, caller-owned)
+    int64_t nm = 0;
+    int64_t nband = 0;
+    char *mws = nullptr;
+    size_t mws_bytes = 0;
+    float *m_pos = nullptr, *m_ub = nullptr, *m_area = nullptr, *m_gain = nullptr;  // sorted order
+    int32_t *m_slot = nullptr;     // [8][nm] band slot of each stencil node
+    int32_t *m_cell = nullptr;     // [nm] base cell, input order
+    int32_t *m_perm = nullptr;     // [nm] input index of sorted sample k
+    uint64_t *tile_mask = nullptr; // [W]
+    int32_t *tile_start = nullptr; // [W]
+    int32_t *band_cell = nullptr;  // [nband]
+    void *band_ru = nullptr;       // [nband] real4 (rho, u)
+    void *band_force = nullptr;    // [nband] real4 (g, 0)
+    std::string err;
+};
+
+namespace lbm {
+
+// Marker workspace carve-up, shared by the size query and lbm_set_solids.
+struct SolidsLayout {
+    size_t pos, ub, area, gain, slot, cell, perm, keys_in, keys_out, idx_in, sort_tmp, sort_tmp_bytes;
+    size_t tile_mask, tile_start, tile_count, scan_tmp, scan_tmp_bytes, band_cell, band_ru, band_force, misc;
+    size_t total;
+};
+hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L);
+
+// launchers (return the first HIP error)
+hipError_t launch_fused(lbm_ctx *c);
+hipError_t launch_band_ib(lbm_ctx *c, double *ftot);  // band pull + interpolation/spreading of the current state
+hipError_t launch_init_eq(lbm_ctx *c, const void *rho, const void *u);
+hipError_t launch_set_pop(lbm_ctx *c, const void *f);
+hipError_t launch_get_pop(lbm_ctx *c, void *f);
+hipError_t launch_macros(lbm_ctx *c, void *rho, void *u);
+hipError_t launch_conserved(lbm_ctx *c);
+hipError_t launch_copy(lbm_ctx *c, void *dst, const void *src, size_t bytes);
+hipError_t launch_zero(lbm_ctx *c, void *dst, size_t bytes);
+hipError_t launch_scalar_io(lbm_ctx *c, float *dst, const float *src, bool to_state);
+hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area, const float *gain,
+                        int *bad_count_host);
+hipError_t launch_solid_maps(lbm_ctx *c, uint8_t *flags, int32_t *cell, int32_t *perm);
+
+}  // namespace lbm

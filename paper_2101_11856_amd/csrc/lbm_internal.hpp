@@ -1,0 +1,432 @@
+// lbm_internal.hpp -- device building blocks shared by the liblbm kernels.
+//
+// Populations are held as deviations d_i = f_i - w_i from the lattice weights
+// in every storage form.  The collision (Sec. 3, Eqs. 4-5) is written in the
+// factorised form the paper's Sec. 4.4.2 argues for (shared monomials
+// u_x^p u_y^q u_z^r computed once): a separable raw-moment transform along x,
+// y and z, a separable binomial shift to central moments about u, relaxation,
+// and the inverse path.  All of it stays in registers; the deviation form keeps
+// every intermediate small, which is what lets FP32 track the FP64 reference.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+#include "lbm.h"
+
+namespace lbm {
+
+constexpr int Q = 27;
+
+// Lattice order (see lbm.h): rest, faces, edges (xy, xz, yz), corners; sign
+// patterns with x fastest inside each group.
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, 1, -1, -1, 1, 1, -1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+
+constexpr int pop_index(int cx, int cy, int cz)
+{
+    for (int i = 0; i < Q; ++i)
+        if (CX[i] == cx && CY[i] == cy && CZ[i] == cz) return i;
+    return -1;
+}
+constexpr int opp(int i) { return pop_index(-CX[i], -CY[i], -CZ[i]); }
+constexpr double weight(int i)
+{
+    return (CX[i] ? 1.0 / 6.0 : 2.0 / 3.0) * (CY[i] ? 1.0 / 6.0 : 2.0 / 3.0) * (CZ[i] ? 1.0 / 6.0 : 2.0 / 3.0);
+}
+
+// population index by (cx+1) + 3 (cy+1) + 9 (cz+1), for run-time lookups
+__device__ __constant__ const int8_t POP_OF[27] = {
+    pop_index(-1, -1, -1), pop_index(0, -1, -1), pop_index(1, -1, -1), pop_index(-1, 0, -1), pop_index(0, 0, -1),
+    pop_index(1, 0, -1),   pop_index(-1, 1, -1), pop_index(0, 1, -1),  pop_index(1, 1, -1),  pop_index(-1, -1, 0),
+    pop_index(0, -1, 0),   pop_index(1, -1, 0),  pop_index(-1, 0, 0),  pop_index(0, 0, 0),   pop_index(1, 0, 0),
+    pop_index(-1, 1, 0),   pop_index(0, 1, 0),   pop_index(1, 1, 0),   pop_index(-1, -1, 1), pop_index(0, -1, 1),
+    pop_index(1, -1, 1),   pop_index(-1, 0, 1),  pop_index(0, 0, 1),   pop_index(1, 0, 1),   pop_index(-1, 1, 1),
+    pop_index(0, 1, 1),    pop_index(1, 1, 1)};
+
+// ---------------------------------------------------------------------------
+// storage codecs
+// ---------------------------------------------------------------------------
+
+template <int ST> struct Store;
+template <> struct Store<LBM_F32> {
+    using T = float;
+    using R = float;
+    __device__ static R dec(T v) { return v; }
+    __device__ static T enc(R v) { return v; }
+};
+template <> struct Store<LBM_F64> {
+    using T = double;
+    using R = double;
+    __device__ static R dec(T v) { return v; }
+    __device__ static T enc(R v) { return v; }
+};
+template <> struct Store<LBM_F16DEV> {
+    using T = uint16_t;
+    using R = float;
+    __device__ static R dec(T v) { return __half2float(__ushort_as_half(v)); }
+    __device__ static T enc(R v) { return __half_as_ushort(__float2half_rn(v)); }
+};
+template <> struct Store<LBM_BF16DEV> {
+    using T = uint16_t;
+    using R = float;
+    __device__ static R dec(T v) { return __uint_as_float(((uint32_t)v) << 16); }
+    __device__ static T enc(R v)
+    {
+        // round to nearest even on the upper 16 bits; NaN stays NaN
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (T)((u >> 16) | 0x40);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (T)(u >> 16);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// geometry shared by every kernel
+// ---------------------------------------------------------------------------
+
+// Work item = one x-segment of 64 nodes of one (y, z) row; a wavefront owns
+// one work item, a 256-thread workgroup four consecutive ones.
+constexpr int SEG = 64;
+constexpr int WAVES_PER_BLOCK = 4;
+
+struct Geom {
+    int nx, ny, nz;
+    int nxp;        // row pitch (elements), multiple of 32
+    int ntx;        // segments per row
+    int64_t plane;  // plane stride (elements)
+    int64_t W;      // number of work items
+    int face[6];
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical blocks so that the x-neighbouring segments of a
+// row (which share cache lines at their edges) land in the same L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb)
+{
+    const int xcd = bid & 7, local = bid >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+__device__ __forceinline__ int face_rank(int f)
+{
+    return f == LBM_NOSLIP ? 4 : f == LBM_INLET ? 3 : f == LBM_OUTFLOW ? 2 : f == LBM_FREESLIP ? 1 : 0;
+}
+
+// Source of the streamed population f*_i at node (x, y, z) under the face
+// rules: plane `pl` at node (sx, sy, sz); `inlet` = add the wall-velocity term
+// of the inlet at row (sy, sz).  At most one inward move (outflow) happens.
+struct PullSrc {
+    int pl, sx, sy, sz, inlet;
+};
+
+__device__ __forceinline__ PullSrc resolve(int i, int x, int y, int z, const Geom &g)
+{
+    const int cx = CX[i], cy = CY[i], cz = CZ[i];
+    int px = x, py = y, pz = z;
+    for (int pass = 0; pass < 2; ++pass) {
+        int sx = px - cx, sy = py - cy, sz = pz - cz;
+        int crossed = 0, best = LBM_PERIODIC, bestrank = 0, baxis = 0, bside = 0;
+        // one axis at a time; every index below is a named scalar (no local arrays)
+        auto axis = [&](int a, int &sv, int n, int fm, int fp) {
+            int side = -1;
+            if (sv < 0) side = 0;
+            else if (sv >= n) side = 1;
+            if (side < 0) return;
+            const int fc = side ? fp : fm;
+            if (fc == LBM_PERIODIC) {
+                sv += side ? -n : n;
+                return;
+            }
+            crossed |= 1 << a;
+            const int r = face_rank(fc);
+            if (r > bestrank) {
+                bestrank = r;
+                best = fc;
+                baxis = a;
+                bside = side;
+            }
+        };
+        axis(0, sx, g.nx, g.face[0], g.face[1]);
+        axis(1, sy, g.ny, g.face[2], g.face[3]);
+        axis(2, sz, g.nz, g.face[4], g.face[5]);
+        if (best == LBM_PERIODIC) return {i, sx, sy, sz, 0};
+        if (best == LBM_NOSLIP) return {opp(i), px, py, pz, 0};
+        if (best == LBM_INLET) return {opp(i), px, py, pz, 1};
+        if (best == LBM_OUTFLOW) {
+            const int d = bside ? -1 : 1;
+            if (baxis == 0) px += d;
+            else if (baxis == 1) py += d;
+            else pz += d;
+            continue;
+        }
+        // free slip: reflect the crossed components, stay on the node's layer
+        int rx = cx, ry = cy, rz = cz;
+        if (crossed & 1) {
+            rx = -rx;
+            sx = px;
+        }
+        if (crossed & 2) {
+            ry = -ry;
+            sy = py;
+        }
+        if (crossed & 4) {
+            rz = -rz;
+            sz = pz;
+        }
+        return {POP_OF[(rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)], sx, sy, sz, 0};
+    }
+    return {i, px, py, pz, 0};  // not reached for valid geometry
+}
+
+__device__ __forceinline__ bool wave_touches_face(int xs, int y, int z, const Geom &g)
+{
+    return (xs == 0 && g.face[0] != LBM_PERIODIC) || (xs == g.ntx - 1 && g.face[1] != LBM_PERIODIC) ||
+           (y == 0 && g.face[2] != LBM_PERIODIC) || (y == g.ny - 1 && g.face[3] != LBM_PERIODIC) ||
+           (z == 0 && g.face[4] != LBM_PERIODIC) || (z == g.nz - 1 && g.face[5] != LBM_PERIODIC);
+}
+
+// Inlet velocity at row (y, z): profile [3][nz][ny] or uniform.
+template <typename R> struct Inlet {
+    const R *prof;
+    R u[3];
+    __device__ R at(int a, int y, int z, int ny, int nz) const
+    {
+        return prof ? prof[((int64_t)a * nz + z) * ny + y] : u[a];
+    }
+};
+
+// One streamed deviation of node (x, y, z), general face-aware path.
+template <int ST, typename R>
+__device__ __forceinline__ R pull_one(int i, const typename Store<ST>::T *__restrict__ in, int x, int y, int z,
+                                      const Geom &g, const Inlet<R> &inl)
+{
+    const PullSrc s = resolve(i, x, y, z, g);
+    const int64_t idx = (int64_t)s.pl * g.plane + ((int64_t)s.sz * g.ny + s.sy) * g.nxp + s.sx;
+    R v = Store<ST>::dec(in[idx]);
+    if (s.inlet) {
+        const R cu = (R)CX[i] * inl.at(0, s.sy, s.sz, g.ny, g.nz) + (R)CY[i] * inl.at(1, s.sy, s.sz, g.ny, g.nz) +
+                     (R)CZ[i] * inl.at(2, s.sy, s.sz, g.ny, g.nz);
+        v += (R)(6.0 * weight(i)) * cu;
+    }
+    return v;
+}
+
+template <int ST, typename R, int... I>
+__device__ __forceinline__ void pull_general_seq(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int x,
+                                                 int y, int z, const Geom &g, const Inlet<R> &inl,
+                                                 std::integer_sequence<int, I...>)
+{
+    ((f[CZ[I] + 1][CY[I] + 1][CX[I] + 1] = pull_one<ST, R>(I, in, x, y, z, g, inl)), ...);
+}
+
+// Pull the 27 deviations of node (x, y, z) into f[cz+1][cy+1][cx+1] with the
+// face rules (population index expanded at compile time).
+template <int ST, typename R>
+__device__ __forceinline__ void pull_general(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int x,
+                                             int y, int z, const Geom &g, const Inlet<R> &inl)
+{
+    pull_general_seq<ST, R>(f, in, x, y, z, g, inl, std::make_integer_sequence<int, Q>{});
+}
+
+// Fast path for a wave away from non-periodic faces: pure pull with periodic
+// wrap; row offsets are wave-uniform.
+template <int ST, typename R>
+__device__ __forceinline__ void pull_interior(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int x,
+                                              int y, int z, const Geom &g)
+{
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    const int xs[3] = {xp, x, xm};  // source x for c_x = -1, 0, +1
+    const int ys[3] = {yp, y, ym};
+    const int zs[3] = {zp, z, zm};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int row = (zs[CZ[i] + 1] * g.ny + ys[CY[i] + 1]) * g.nxp;
+        const typename Store<ST>::T *pl = in + (int64_t)i * g.plane + row;
+        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(pl[xs[CX[i] + 1]]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// collision (Eqs. 4-5) in deviation form
+// ---------------------------------------------------------------------------
+
+template <typename R> struct Rates {
+    R s_nu, s_b, s3, s4, s5, s6;
+};
+
+// Raw moments along one axis of the line (v(-1), v(0), v(+1)) -> (m0, m1, m2).
+template <typename R> __device__ __forceinline__ void raw3(R &a, R &b, R &c)
+{
+    const R s = c + a, t = c - a;
+    a = s + b;
+    b = t;
+    c = s;
+}
+// Central shift along one axis: (m0, m1, m2) -> (k0, k1, k2) about u.
+template <typename R> __device__ __forceinline__ void shift3(R &m0, R &m1, R &m2, R u)
+{
+    const R k1 = m1 - u * m0;
+    m2 = m2 - u * (m1 + k1);
+    m1 = k1;
+}
+// Inverse shift: (k0, k1, k2) -> (m0, m1, m2).
+template <typename R> __device__ __forceinline__ void unshift3(R &k0, R &k1, R &k2, R u)
+{
+    const R m1 = k1 + u * k0;
+    k2 = k2 + u * (k1 + m1);
+    k1 = m1;
+}
+// Inverse raw transform: (m0, m1, m2) -> (v(-1), v(0), v(+1)).
+template <typename R> __device__ __forceinline__ void iraw3(R &a, R &b, R &c)
+{
+    const R h = (R)0.5 * c;
+    const R m0 = a, m1 = b, m2 = c;
+    a = h - (R)0.5 * m1;
+    c = h + (R)0.5 * m1;
+    b = m0 - m2;
+}
+
+// Apply a 3-point line operation to the 9 lines of f[z][y][x] along x, y or z.
+template <typename R, typename Op> __device__ __forceinline__ void lines_x(R (&f)[3][3][3], Op op)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) op(f[a][b][0], f[a][b][1], f[a][b][2]);
+}
+template <typename R, typename Op> __device__ __forceinline__ void lines_y(R (&f)[3][3][3], Op op)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) op(f[a][0][b], f[a][1][b], f[a][2][b]);
+}
+template <typename R, typename Op> __device__ __forceinline__ void lines_z(R (&f)[3][3][3], Op op)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) op(f[0][a][b], f[1][a][b], f[2][a][b]);
+}
+
+// Macroscopic values of a pulled node: rho = 1 + sum d, j = sum c d (Eq. 2).
+template <typename R> struct Macro {
+    R drho, jx, jy, jz;
+};
+
+// f holds the pulled deviations; on return f holds the post-collision
+// deviations and (rho, u) the density and half-force velocity used.
+template <typename R>
+__device__ __forceinline__ void collide(R (&f)[3][3][3], R Fx, R Fy, R Fz, const Rates<R> &rt, R &rho_o, R &ux_o,
+                                        R &uy_o, R &uz_o)
+{
+    const R third = (R)(1.0 / 3.0), ninth = (R)(1.0 / 9.0), t27 = (R)(1.0 / 27.0);
+    // raw moments of d (index [mz][my][mx])
+    auto raw = [](R &a, R &b, R &c) { raw3(a, b, c); };
+    lines_x(f, raw);
+    lines_y(f, raw);
+    lines_z(f, raw);
+    const R drho = f[0][0][0];
+    const R rho = (R)1 + drho;
+    const R inv = (R)1 / rho;
+    const R ux = (f[0][0][1] + (R)0.5 * Fx) * inv;
+    const R uy = (f[0][1][0] + (R)0.5 * Fy) * inv;
+    const R uz = (f[1][0][0] + (R)0.5 * Fz) * inv;
+    rho_o = rho;
+    ux_o = ux;
+    uy_o = uy;
+    uz_o = uz;
+    // central moments of d about u
+    lines_x(f, [ux](R &a, R &b, R &c) { shift3(a, b, c, ux); });
+    lines_y(f, [uy](R &a, R &b, R &c) { shift3(a, b, c, uy); });
+    lines_z(f, [uz](R &a, R &b, R &c) { shift3(a, b, c, uz); });
+
+    // Delta = kappa(w; u) - kappa_eq(rho): equilibrium offsets written so that
+    // no large terms cancel.  kappa - kappa_eq = kappa(d) + Delta.
+    const R x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
+    const R px = third + x2, py = third + y2, pz = third + z2;
+    const R dr3 = drho * third, dr9 = drho * ninth;
+    // order 1: conserved (rate 0), forcing adds F
+    f[0][0][1] += Fx;
+    f[0][1][0] += Fy;
+    f[1][0][0] += Fz;
+    // order 2, off-diagonal: shear rate
+    f[0][1][1] -= rt.s_nu * (f[0][1][1] + ux * uy);
+    f[1][0][1] -= rt.s_nu * (f[1][0][1] + ux * uz);
+    f[1][1][0] -= rt.s_nu * (f[1][1][0] + uy * uz);
+    // order 2, diagonal: deviator at s_nu, trace at s_b
+    {
+        const R nxx = f[0][0][2] + x2 - dr3, nyy = f[0][2][0] + y2 - dr3, nzz = f[2][0][0] + z2 - dr3;
+        const R tr = (rt.s_b - rt.s_nu) * third * (nxx + nyy + nzz);
+        f[0][0][2] -= rt.s_nu * nxx + tr;
+        f[0][2][0] -= rt.s_nu * nyy + tr;
+        f[2][0][0] -= rt.s_nu * nzz + tr;
+    }
+    // order 3 (forcing term F cs^2 on the (1,2,0) family)
+    {
+        const R s = rt.s3, h = (R)1 - (R)0.5 * s;
+        f[0][2][1] += -s * (f[0][2][1] - ux * py) + h * third * Fx;  // (1,2,0)
+        f[2][0][1] += -s * (f[2][0][1] - ux * pz) + h * third * Fx;  // (1,0,2)
+        f[0][1][2] += -s * (f[0][1][2] - uy * px) + h * third * Fy;  // (2,1,0)
+        f[2][1][0] += -s * (f[2][1][0] - uy * pz) + h * third * Fy;  // (0,1,2)
+        f[1][0][2] += -s * (f[1][0][2] - uz * px) + h * third * Fz;  // (2,0,1)
+        f[1][2][0] += -s * (f[1][2][0] - uz * py) + h * third * Fz;  // (0,2,1)
+        f[1][1][1] -= s * (f[1][1][1] - ux * uy * uz);               // (1,1,1)
+    }
+    // order 4
+    {
+        const R s = rt.s4;
+        f[0][2][2] -= s * (f[0][2][2] + (x2 + y2) * third + x2 * y2 - dr9);  // (2,2,0)
+        f[2][0][2] -= s * (f[2][0][2] + (x2 + z2) * third + x2 * z2 - dr9);  // (2,0,2)
+        f[2][2][0] -= s * (f[2][2][0] + (y2 + z2) * third + y2 * z2 - dr9);  // (0,2,2)
+        f[1][1][2] -= s * (f[1][1][2] + px * uy * uz);                       // (2,1,1)
+        f[1][2][1] -= s * (f[1][2][1] + py * ux * uz);                       // (1,2,1)
+        f[2][1][1] -= s * (f[2][1][1] + pz * ux * uy);                       // (1,1,2)
+    }
+    // order 5 (forcing term F cs^4 on the (1,2,2) family)
+    {
+        const R s = rt.s5, h = (R)1 - (R)0.5 * s;
+        f[2][2][1] += -s * (f[2][2][1] - ux * py * pz) + h * ninth * Fx;  // (1,2,2)
+        f[2][1][2] += -s * (f[2][1][2] - uy * px * pz) + h * ninth * Fy;  // (2,1,2)
+        f[1][2][2] += -s * (f[1][2][2] - uz * px * py) + h * ninth * Fz;  // (2,2,1)
+    }
+    // order 6
+    {
+        const R d6 = (x2 * y2 + x2 * z2 + y2 * z2) * third + (x2 + y2 + z2) * ninth + x2 * y2 * z2 - drho * t27;
+        f[2][2][2] -= rt.s6 * (f[2][2][2] + d6);
+    }
+    // back to raw moments, then to populations
+    lines_z(f, [uz](R &a, R &b, R &c) { unshift3(a, b, c, uz); });
+    lines_y(f, [uy](R &a, R &b, R &c) { unshift3(a, b, c, uy); });
+    lines_x(f, [ux](R &a, R &b, R &c) { unshift3(a, b, c, ux); });
+    auto iraw = [](R &a, R &b, R &c) { iraw3(a, b, c); };
+    lines_z(f, iraw);
+    lines_y(f, iraw);
+    lines_x(f, iraw);
+}
+
+// rho - 1 and j of pulled deviations (no transform of the rest).
+template <typename R> __device__ __forceinline__ Macro<R> moments01(const R (&f)[3][3][3])
+{
+    Macro<R> m{0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R v = f[CZ[i] + 1][CY[i] + 1][CX[i] + 1];
+        m.drho += v;
+        if (CX[i]) m.jx += CX[i] > 0 ? v : -v;
+        if (CY[i]) m.jy += CY[i] > 0 ? v : -v;
+        if (CZ[i]) m.jz += CZ[i] > 0 ? v : -v;
+    }
+    return m;
+}
+
+}  // namespace lbm

@@ -1,0 +1,336 @@
+// lbm_step.hip -- the per-step kernels of liblbm (Alg. 2 of the paper):
+//   k_band   (a)+(b) on the immersed-boundary band only: pull + rho, u
+//   k_ib     (c) interpolation, penalty force, spreading by scattering
+//   k_fused  (a)+(b)+(d)+(e) for every node: pull with face rules, rho and u,
+//            band force, central-moment collision, store
+#include "lbm_ctx.hpp"
+
+namespace lbm {
+
+template <typename R> struct R4T;
+template <> struct R4T<float> {
+    using type = float4;
+};
+template <> struct R4T<double> {
+    using type = double4;
+};
+
+template <int ST> struct StepParams {
+    using R = typename Store<ST>::R;
+    using T = typename Store<ST>::T;
+    using R4 = typename R4T<R>::type;
+    Geom g;
+    const T *__restrict__ fin;
+    T *__restrict__ fout;
+    Rates<R> rt;
+    R body[3];
+    Inlet<R> inlet;
+    const uint64_t *__restrict__ tile_mask;
+    const int32_t *__restrict__ tile_start;
+    const R4 *__restrict__ band_force;
+    const float *__restrict__ sc_in;
+    float *__restrict__ sc_out;
+    int sc_h;
+};
+
+// ---------------------------------------------------------------------------
+// passive scalar: first-order upwind by the collision velocity; periodic
+// wrap or zero gradient at faces; held at 1 on inlet nodes below sc_h
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int nb_coord(int v, int n, bool periodic)
+{
+    if (v < 0) return periodic ? v + n : 0;
+    if (v >= n) return periodic ? v - n : n - 1;
+    return v;
+}
+
+template <int ST>
+__device__ __forceinline__ void scalar_update(const StepParams<ST> &P, int x, int y, int z, float ux, float uy,
+                                              float uz, bool active)
+{
+    const Geom &g = P.g;
+    auto at = [&](int xx, int yy, int zz) {
+        xx = nb_coord(xx, g.nx, g.face[0] == LBM_PERIODIC);
+        yy = nb_coord(yy, g.ny, g.face[2] == LBM_PERIODIC);
+        zz = nb_coord(zz, g.nz, g.face[4] == LBM_PERIODIC);
+        return P.sc_in[((int64_t)zz * g.ny + yy) * g.nxp + xx];
+    };
+    const float s0 = at(x, y, z);
+    float v = s0;
+    v -= ux > 0.f ? ux * (s0 - at(x - 1, y, z)) : ux * (at(x + 1, y, z) - s0);
+    v -= uy > 0.f ? uy * (s0 - at(x, y - 1, z)) : uy * (at(x, y + 1, z) - s0);
+    v -= uz > 0.f ? uz * (s0 - at(x, y, z - 1)) : uz * (at(x, y, z + 1) - s0);
+    if (x == 0 && g.face[0] == LBM_INLET && y < P.sc_h) v = 1.f;
+    if (active) P.sc_out[((int64_t)z * g.ny + y) * g.nxp + x] = v;
+}
+
+// ---------------------------------------------------------------------------
+// fused step
+// ---------------------------------------------------------------------------
+template <int ST, bool BAND, bool SCALAR>
+__global__ void __launch_bounds__(256) k_fused(const StepParams<ST> P)
+{
+    using R = typename Store<ST>::R;
+    const Geom &g = P.g;
+    const int lane = threadIdx.x & (SEG - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / SEG);
+    const int64_t w = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wv;
+    if (w >= g.W) return;
+    const int xs = (int)(w % g.ntx);
+    const int64_t row = w / g.ntx;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    const int x = xs * SEG + lane;
+    const bool active = x < g.nx;
+    const int xc = active ? x : g.nx - 1;
+
+    R f[3][3][3];
+    if (wave_touches_face(xs, y, z, g)) pull_general<ST>(f, P.fin, xc, y, z, g, P.inlet);
+    else pull_interior<ST>(f, P.fin, xc, y, z, g);
+
+    R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
+    if (BAND) {
+        const uint64_t mask = P.tile_mask[w];
+        if (mask != 0 && ((mask >> lane) & 1ull)) {
+            const int slot = P.tile_start[w] + __popcll(mask & ((1ull << lane) - 1ull));
+            const auto F = P.band_force[slot];
+            Fx += F.x;
+            Fy += F.y;
+            Fz += F.z;
+        }
+    }
+    R rho, ux, uy, uz;
+    collide(f, Fx, Fy, Fz, P.rt, rho, ux, uy, uz);
+    if (active) {
+        const int64_t base = ((int64_t)z * g.ny + y) * g.nxp + x;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            __builtin_nontemporal_store(Store<ST>::enc(f[CZ[i] + 1][CY[i] + 1][CX[i] + 1]),
+                                        P.fout + (int64_t)i * g.plane + base);
+    }
+    if (SCALAR) scalar_update<ST>(P, xc, y, z, (float)ux, (float)uy, (float)uz, active);
+}
+
+// ---------------------------------------------------------------------------
+// band pre-pass: streamed rho and u0 = j/rho of every band node; clears the
+// band force and the force total
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ void __launch_bounds__(256)
+    k_band(const StepParams<ST> P, const int32_t *__restrict__ band_cell, int64_t nband,
+           typename StepParams<ST>::R4 *__restrict__ band_ru, typename StepParams<ST>::R4 *__restrict__ band_force,
+           double *__restrict__ ftot)
+{
+    using R = typename Store<ST>::R;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b == 0) {
+        ftot[0] = 0.0;
+        ftot[1] = 0.0;
+        ftot[2] = 0.0;
+    }
+    if (b >= nband) return;
+    const Geom &g = P.g;
+    const int64_t cell = band_cell[b];
+    const int x = (int)(cell % g.nx);
+    const int64_t r = cell / g.nx;
+    const int y = (int)(r % g.ny), z = (int)(r / g.ny);
+    R f[3][3][3];
+    pull_general<ST>(f, P.fin, x, y, z, g, P.inlet);
+    const Macro<R> m = moments01(f);
+    const R rho = (R)1 + m.drho, inv = (R)1 / rho;
+    typename StepParams<ST>::R4 v;
+    v.x = rho;
+    v.y = m.jx * inv;
+    v.z = m.jy * inv;
+    v.w = m.jz * inv;
+    band_ru[b] = v;
+    v.x = v.y = v.z = v.w = (R)0;
+    band_force[b] = v;
+}
+
+// ---------------------------------------------------------------------------
+// immersed boundary: one lane per sorted sample
+// ---------------------------------------------------------------------------
+template <typename R> struct IbParams {
+    using R4 = typename R4T<R>::type;
+    int64_t n;
+    const float *__restrict__ pos;   // [3][n] sorted
+    const float *__restrict__ ub;    // [3][n]
+    const float *__restrict__ area;  // [n]
+    const float *__restrict__ gain;  // [n]
+    const int32_t *__restrict__ slot;  // [8][n]
+    const R4 *__restrict__ band_ru;
+    R4 *__restrict__ band_force;
+    double *__restrict__ ftot;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_ib(const IbParams<R> P)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool valid = s < P.n;
+    const int64_t sc = valid ? s : P.n - 1;
+    const int64_t n = P.n;
+
+    // Eq. (6): trilinear weights of the 2x2x2 stencil, delta = dx + 2 dy + 4 dz
+    R t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float p = P.pos[a * n + sc];
+        t[a] = (R)(p - floorf(p));
+    }
+    int32_t sl[8];
+    R K[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        sl[d] = P.slot[(int64_t)d * n + sc];
+        K[d] = ((d & 1) ? t[0] : (R)1 - t[0]) * ((d & 2) ? t[1] : (R)1 - t[1]) * ((d & 4) ? t[2] : (R)1 - t[2]);
+    }
+    R rs = 0, us[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const auto v = P.band_ru[sl[d]];
+        rs += K[d] * v.x;
+        us[0] += K[d] * v.y;
+        us[1] += K[d] * v.z;
+        us[2] += K[d] * v.w;
+    }
+    // Eq. (7) with the sample's gain; Eq. (8) carries the area weight
+    const R gam = (R)P.gain[sc], ar = (R)P.area[sc];
+    R aG[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) aG[a] = valid ? ar * gam * rs * ((R)P.ub[a * n + sc] - us[a]) : (R)0;
+
+    // FP64 total force: wave reduction, one atomic per wave and component
+    double tot[3] = {(double)aG[0], (double)aG[1], (double)aG[2]};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) tot[a] += __shfl_down(tot[a], off, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) unsafeAtomicAdd(P.ftot + a, tot[a]);
+    }
+
+    // Eq. (8) by scattering: samples of one base cell are contiguous in the
+    // sorted order and share all 8 targets; a segmented suffix sum over the
+    // run leaves the run total in its first lane, which alone adds it.
+    const int key = valid ? sl[0] : -1;  // slot of the base cell identifies the run
+    R v[8][3];
+#pragma unroll
+    for (int d = 0; d < 8; ++d)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[d][a] = K[d] * aG[a];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int k2 = __shfl_down(key, off, 64);
+        const bool same = (lane + off < 64) && (k2 == key);
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R o = __shfl_down(v[d][a], off, 64);
+                if (same) v[d][a] += o;
+            }
+    }
+    const int kprev = __shfl_up(key, 1, 64);
+    const bool head = valid && (lane == 0 || kprev != key);
+    if (head) {
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            R *dst = reinterpret_cast<R *>(P.band_force + sl[d]);
+            unsafeAtomicAdd(dst + 0, v[d][0]);
+            unsafeAtomicAdd(dst + 1, v[d][1]);
+            unsafeAtomicAdd(dst + 2, v[d][2]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int ST> static StepParams<ST> make_params(lbm_ctx *c)
+{
+    using R = typename Store<ST>::R;
+    using T = typename Store<ST>::T;
+    StepParams<ST> P{};
+    P.g = c->g;
+    P.fin = static_cast<const T *>(c->fA);
+    P.fout = static_cast<T *>(c->fB);
+    P.rt = {(R)c->s_nu, (R)c->s_b, (R)c->s_h[0], (R)c->s_h[1], (R)c->s_h[2], (R)c->s_h[3]};
+    for (int a = 0; a < 3; ++a) {
+        P.body[a] = (R)c->p.body_force[a];
+        P.inlet.u[a] = (R)c->p.u_in[a];
+    }
+    P.inlet.prof = static_cast<const R *>(c->p.inlet_profile);
+    P.tile_mask = c->tile_mask;
+    P.tile_start = c->tile_start;
+    P.band_force = static_cast<const typename StepParams<ST>::R4 *>(c->band_force);
+    P.sc_in = c->scA;
+    P.sc_out = c->scB;
+    P.sc_h = c->p.scalar_inlet_height;
+    return P;
+}
+
+static inline unsigned blocks_for_items(int64_t W) { return (unsigned)((W + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK); }
+
+template <int ST> static hipError_t fused_st(lbm_ctx *c)
+{
+    const StepParams<ST> P = make_params<ST>(c);
+    const bool band = c->nm > 0, scalar = c->p.passive_scalar != 0;
+    const dim3 grid(blocks_for_items(c->g.W)), block(256);
+    if (band && scalar) hipLaunchKernelGGL((k_fused<ST, true, true>), grid, block, 0, c->stream, P);
+    else if (band) hipLaunchKernelGGL((k_fused<ST, true, false>), grid, block, 0, c->stream, P);
+    else if (scalar) hipLaunchKernelGGL((k_fused<ST, false, true>), grid, block, 0, c->stream, P);
+    else hipLaunchKernelGGL((k_fused<ST, false, false>), grid, block, 0, c->stream, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused(lbm_ctx *c)
+{
+    switch (c->p.storage) {
+    case LBM_F32: return fused_st<LBM_F32>(c);
+    case LBM_F16DEV: return fused_st<LBM_F16DEV>(c);
+    case LBM_BF16DEV: return fused_st<LBM_BF16DEV>(c);
+    case LBM_F64: return fused_st<LBM_F64>(c);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int ST> static hipError_t band_ib_st(lbm_ctx *c, double *ftot)
+{
+    using R = typename Store<ST>::R;
+    using R4 = typename StepParams<ST>::R4;
+    const StepParams<ST> P = make_params<ST>(c);
+    const unsigned nb = (unsigned)((c->nband + 255) / 256);
+    hipLaunchKernelGGL((k_band<ST>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, P, c->band_cell, c->nband,
+                       static_cast<R4 *>(c->band_ru), static_cast<R4 *>(c->band_force), ftot);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    IbParams<R> Q{};
+    Q.n = c->nm;
+    Q.pos = c->m_pos;
+    Q.ub = c->m_ub;
+    Q.area = c->m_area;
+    Q.gain = c->m_gain;
+    Q.slot = c->m_slot;
+    Q.band_ru = static_cast<const R4 *>(c->band_ru);
+    Q.band_force = static_cast<R4 *>(c->band_force);
+    Q.ftot = ftot;
+    hipLaunchKernelGGL((k_ib<R>), dim3((unsigned)((c->nm + 255) / 256)), dim3(256), 0, c->stream, Q);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_ib(lbm_ctx *c, double *ftot)
+{
+    if (c->nm <= 0) return hipSuccess;
+    switch (c->p.storage) {
+    case LBM_F32: return band_ib_st<LBM_F32>(c, ftot);
+    case LBM_F16DEV: return band_ib_st<LBM_F16DEV>(c, ftot);
+    case LBM_BF16DEV: return band_ib_st<LBM_BF16DEV>(c, ftot);
+    case LBM_F64: return band_ib_st<LBM_F64>(c, ftot);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

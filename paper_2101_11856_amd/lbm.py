@@ -1,0 +1,273 @@
+"""ctypes binding of liblbm (include/lbm.h).
+
+Argument marshalling only: PyTorch provides device memory and the stream,
+every step of the method runs in the library's HIP kernels.  If liblbm.so is
+missing this module raises at import time; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+PERIODIC, NOSLIP, FREESLIP, INLET, OUTFLOW = 0, 1, 2, 3, 4
+F32, F16DEV, BF16DEV, F64 = 0, 1, 2, 3
+STORAGE = {"f32": F32, "f16": F16DEV, "bf16": BF16DEV, "f64": F64}
+STATUS = {0: "LBM_OK", 1: "LBM_E_INVAL", 2: "LBM_E_NOMEM", 3: "LBM_E_HIP", 4: "LBM_E_NONFINITE",
+          5: "LBM_E_STATE", 6: "LBM_E_UNSUPPORTED"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("nu", C.c_double),
+        ("face", C.c_int32 * 6),
+        ("u_in", C.c_double * 3),
+        ("inlet_profile", C.c_void_p),
+        ("body_force", C.c_double * 3),
+        ("s_bulk", C.c_double),
+        ("s_high", C.c_double * 4),
+        ("storage", C.c_int32),
+        ("passive_scalar", C.c_int32),
+        ("scalar_inlet_height", C.c_int32),
+    ]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950) first")
+
+_L = C.CDLL(LIB_PATH)
+_vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+_pp = C.POINTER(Params)
+_SIG = {
+    "lbm_default_params": [_pp, _i32, _i32, _i32, C.c_double],
+    "lbm_workspace_size": [_pp, C.POINTER(_sz)],
+    "lbm_create": [_pp, _vp, _sz, _vp, C.POINTER(_vp)],
+    "lbm_set_stream": [_vp, _vp],
+    "lbm_init_equilibrium": [_vp, _vp, _vp],
+    "lbm_set_populations": [_vp, _vp],
+    "lbm_get_populations": [_vp, _vp],
+    "lbm_set_scalar": [_vp, _vp],
+    "lbm_get_scalar": [_vp, _vp],
+    "lbm_solids_ws_size": [_vp, _i64, C.POINTER(_sz)],
+    "lbm_set_solids": [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz],
+    "lbm_step": [_vp, _i32],
+    "lbm_macros": [_vp, _vp, _vp],
+    "lbm_conserved": [_vp, C.POINTER(C.c_double)],
+    "lbm_ib_force": [_vp, C.POINTER(C.c_double)],
+    "lbm_ib_force_eval": [_vp, C.POINTER(C.c_double)],
+    "lbm_solid_maps": [_vp, _vp, _vp, _vp],
+    "lbm_state_bytes": [_vp, C.POINTER(_sz)],
+    "lbm_checkpoint": [_vp, _vp],
+    "lbm_restore": [_vp, _vp],
+}
+for _name, _args in _SIG.items():
+    _fn = getattr(_L, _name)
+    _fn.argtypes = _args
+    _fn.restype = C.c_int
+_L.lbm_destroy.argtypes = [_vp]
+_L.lbm_destroy.restype = None
+_L.lbm_last_error.argtypes = [_vp]
+_L.lbm_last_error.restype = C.c_char_p
+_L.lbm_version.restype = C.c_char_p
+
+lib = _L
+
+
+def _check(status: int, ctx=None):
+    if status != 0:
+        raise LbmError(status, _L.lbm_last_error(ctx).decode())
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def make_params(nx, ny, nz, nu, faces=(PERIODIC,) * 6, u_in=(0.0, 0.0, 0.0), body=(0.0, 0.0, 0.0),
+                s_bulk=1.0, s_high=(1.0, 1.0, 1.0, 1.0), storage="f32", scalar=False,
+                scalar_inlet_height=0) -> Params:
+    p = Params()
+    _check(_L.lbm_default_params(C.byref(p), nx, ny, nz, float(nu)))
+    for k in range(6):
+        p.face[k] = int(faces[k])
+    for a in range(3):
+        p.u_in[a] = float(u_in[a])
+        p.body_force[a] = float(body[a])
+    p.s_bulk = float(s_bulk)
+    for k in range(4):
+        p.s_high[k] = float(s_high[k])
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.passive_scalar = 1 if scalar else 0
+    p.scalar_inlet_height = int(scalar_inlet_height)
+    return p
+
+
+def workspace_size(p: Params) -> int:
+    n = C.c_size_t()
+    _check(_L.lbm_workspace_size(C.byref(p), C.byref(n)))
+    return n.value
+
+
+class Solver:
+    """One lattice Boltzmann domain on the current CUDA/HIP device.
+
+    Arrays follow the library layout: scalar fields [nz, ny, nx], vector fields
+    [3, nz, ny, nx], populations [27, nz, ny, nx], samples [3, n].  The real
+    dtype is float32, or float64 for storage "f64".
+    """
+
+    def __init__(self, nx, ny, nz, nu, faces=(PERIODIC,) * 6, u_in=(0.0, 0.0, 0.0), inlet_profile=None,
+                 body=(0.0, 0.0, 0.0), s_bulk=1.0, s_high=(1.0, 1.0, 1.0, 1.0), storage="f32", scalar=False,
+                 scalar_inlet_height=0, device="cuda", stream=None):
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+        self.device = torch.device(device)
+        self.storage = storage
+        self.real = torch.float64 if storage == "f64" else torch.float32
+        self._p = make_params(nx, ny, nz, nu, faces, u_in, body, s_bulk, s_high, storage, scalar, scalar_inlet_height)
+        self._inlet = None
+        if inlet_profile is not None:
+            self._inlet = self._real(inlet_profile, (3, nz, ny))
+            self._p.inlet_profile = self._inlet.data_ptr()
+        self.ws = torch.empty(workspace_size(self._p), dtype=torch.uint8, device=self.device)
+        if self.ws.data_ptr() % 256:
+            raise RuntimeError("workspace allocation is not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(_L.lbm_create(C.byref(self._p), _ptr(self.ws), self.ws.numel(), C.c_void_p(self.stream.cuda_stream),
+                             C.byref(h)))
+        self._h = h
+        self._mws = None
+        self.n_markers = 0
+
+    # ------------------------------------------------------------------
+    def _real(self, t, shape=None) -> torch.Tensor:
+        t = torch.as_tensor(t, device=self.device).to(self.real).contiguous()
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            t = t.reshape(shape)
+        return t
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _L.lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_inlet_profile(self, prof):
+        """Replace the contents of the inlet profile given at construction."""
+        if self._inlet is None:
+            raise LbmError(5, "solver was created without an inlet profile")
+        self._inlet.copy_(self._real(prof, self._inlet.shape))
+
+    # ------------------------------------------------------------------
+    def init_equilibrium(self, rho, u):
+        self._rho0 = self._real(rho, self.shape)
+        self._u0 = self._real(u, (3,) + self.shape)
+        _check(_L.lbm_init_equilibrium(self._h, _ptr(self._rho0), _ptr(self._u0)), self._h)
+
+    def set_populations(self, f):
+        self._f0 = self._real(f, (27,) + self.shape)
+        _check(_L.lbm_set_populations(self._h, _ptr(self._f0)), self._h)
+
+    def get_populations(self) -> torch.Tensor:
+        f = torch.empty((27,) + self.shape, dtype=self.real, device=self.device)
+        _check(_L.lbm_get_populations(self._h, _ptr(f)), self._h)
+        return f
+
+    def set_scalar(self, s):
+        self._s0 = torch.as_tensor(s, device=self.device).to(torch.float32).contiguous().reshape(self.shape)
+        _check(_L.lbm_set_scalar(self._h, _ptr(self._s0)), self._h)
+
+    def get_scalar(self) -> torch.Tensor:
+        s = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        _check(_L.lbm_get_scalar(self._h, _ptr(s)), self._h)
+        return s
+
+    def set_solids(self, xyz, ub=None, area=None, gain=None):
+        f32 = lambda t: None if t is None else torch.as_tensor(t, device=self.device).to(torch.float32).contiguous()
+        xyz, ub, area, gain = f32(xyz), f32(ub), f32(area), f32(gain)
+        n = 0 if xyz is None else int(xyz.shape[1])
+        if n == 0:
+            _check(_L.lbm_set_solids(self._h, 0, None, None, None, None, None, 0), self._h)
+            self.n_markers = 0
+            return
+        if ub is None:
+            ub = torch.zeros((3, n), dtype=torch.float32, device=self.device)
+        nb = C.c_size_t()
+        _check(_L.lbm_solids_ws_size(self._h, n, C.byref(nb)), self._h)
+        self._mws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        _check(_L.lbm_set_solids(self._h, n, _ptr(xyz), _ptr(ub), _ptr(area), _ptr(gain), _ptr(self._mws),
+                                 self._mws.numel()), self._h)
+        self.n_markers = n
+
+    def step(self, n: int = 1):
+        _check(_L.lbm_step(self._h, int(n)), self._h)
+
+    def macros(self):
+        rho = torch.empty(self.shape, dtype=self.real, device=self.device)
+        u = torch.empty((3,) + self.shape, dtype=self.real, device=self.device)
+        _check(_L.lbm_macros(self._h, _ptr(rho), _ptr(u)), self._h)
+        return rho, u
+
+    def conserved(self) -> np.ndarray:
+        out = (C.c_double * 4)()
+        _check(_L.lbm_conserved(self._h, out), self._h)
+        return np.array(out[:])
+
+    def ib_force(self) -> np.ndarray:
+        out = (C.c_double * 3)()
+        _check(_L.lbm_ib_force(self._h, out), self._h)
+        return np.array(out[:])
+
+    def ib_force_eval(self) -> np.ndarray:
+        out = (C.c_double * 3)()
+        _check(_L.lbm_ib_force_eval(self._h, out), self._h)
+        return np.array(out[:])
+
+    def solid_maps(self):
+        flags = torch.empty(self.shape, dtype=torch.uint8, device=self.device)
+        n = max(self.n_markers, 1)
+        cell = torch.empty(n, dtype=torch.int32, device=self.device)
+        perm = torch.empty(n, dtype=torch.int32, device=self.device)
+        _check(_L.lbm_solid_maps(self._h, _ptr(flags), _ptr(cell), _ptr(perm)), self._h)
+        return flags, cell[: self.n_markers], perm[: self.n_markers]
+
+    def state_bytes(self) -> int:
+        n = C.c_size_t()
+        _check(_L.lbm_state_bytes(self._h, C.byref(n)), self._h)
+        return n.value
+
+    def checkpoint(self, dst: torch.Tensor | None = None) -> torch.Tensor:
+        if dst is None:
+            dst = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        _check(_L.lbm_checkpoint(self._h, _ptr(dst)), self._h)
+        return dst
+
+    def restore(self, src: torch.Tensor):
+        if src.numel() * src.element_size() < self.state_bytes():
+            raise LbmError(1, "snapshot too small")
+        _check(_L.lbm_restore(self._h, _ptr(src)), self._h)
+
+
+def version() -> str:
+    return _L.lbm_version().decode()

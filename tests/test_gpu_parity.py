@@ -1,0 +1,274 @@
+"""GPU parity: the HIP library (through its C-ABI) against the FP64 CPU oracle
+on identical seeded inputs.
+
+Gates (from the method's stated targets): FP32 populations, rel-L2 on rho and u
+<= 1e-5 after 100 steps; FP64 storage to round-off; integer sample maps
+bit-exact.  Sizes span several 64-node segments with a ragged tail.
+"""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2101_11856_amd import synth
+from tests.gpu_cases import FS, IN, NS, OUT, P, gpu_solver, random_populations, rel_l2, rel_l2_dev, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+FP32_GATE = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_11856_amd import lbm  # noqa: F401  (fails loudly if liblbm.so is missing)
+    yield
+
+
+# ---------------------------------------------------------------------------
+# Taylor-Green 32^3, 100 steps (the small parity configuration)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def tg_oracle():
+    rho, u = synth.taylor_green(32, 0.05, dtype=np.float32)
+    S = O.OracleSim(32, 32, 32, 0.01)
+    S.init_equilibrium(rho.astype(np.float64), u.astype(np.float64))
+    S.step(100)
+    r, uu = S.macros()
+    return rho, u, r, uu, S.conserved()
+
+
+@pytest.mark.parametrize("storage,gate", [("f32", FP32_GATE), ("f64", 1e-12)])
+def test_taylor_green_100_steps(tg_oracle, storage, gate):
+    rho, u, r_ref, u_ref, _ = tg_oracle
+    say(f"taylor-green 32^3 storage={storage}")
+    s = gpu_solver(32, 32, 32, 0.01, storage=storage)
+    s.init_equilibrium(rho, u)
+    s.step(100)
+    r, uu = s.macros()
+    r, uu = to_np(r), to_np(uu)
+    e_u, e_r = rel_l2(uu, u_ref), rel_l2(r, r_ref)
+    say(f"  rel-L2 u={e_u:.3e} rho={e_r:.3e} rho-dev={rel_l2_dev(r, r_ref):.3e}")
+    assert e_u <= gate and e_r <= gate
+
+
+def test_taylor_green_conserved_fp64(tg_oracle):
+    _, _, _, _, cons_ref = tg_oracle
+    rho, u = synth.taylor_green(32, 0.05, dtype=np.float32)
+    s = gpu_solver(32, 32, 32, 0.01, storage="f64")
+    s.init_equilibrium(rho.astype(np.float64), u.astype(np.float64))
+    c0 = s.conserved()
+    s.step(100)
+    c1 = s.conserved()
+    assert abs(c1[0] - cons_ref[0]) / cons_ref[0] < 1e-13
+    assert np.abs(c1[1:] - cons_ref[1:]).max() < 1e-11
+    assert abs(c1[0] - c0[0]) / c0[0] < 1e-13 and np.abs(c1[1:] - c0[1:]).max() < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# one step from an arbitrary state: every population, every face rule
+# ---------------------------------------------------------------------------
+FACE_CASES = [
+    ("periodic-ragged", (70, 9, 7), (P, P, P, P, P, P), False),
+    ("inlet-outflow", (70, 6, 5), (IN, OUT, P, P, P, P), True),
+    ("city-like", (66, 7, 5), (IN, OUT, NS, FS, P, P), True),
+    ("channel", (20, 6, 6), (IN, OUT, NS, NS, NS, NS), True),
+    ("walls", (9, 8, 6), (P, P, FS, FS, NS, NS), False),
+    ("thin-x", (1, 5, 3), (P, P, P, P, P, P), False),
+]
+
+
+def _inlet(ny, nz, seed=5):
+    rng = np.random.default_rng(seed)
+    prof = np.zeros((3, nz, ny))
+    prof[0] = 0.04 + 0.01 * rng.standard_normal((nz, ny))
+    prof[1] = 0.005 * rng.standard_normal((nz, ny))
+    return prof.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("name,shape,faces,profile", FACE_CASES, ids=[c[0] for c in FACE_CASES])
+def test_one_step_all_populations_fp64(name, shape, faces, profile):
+    nx, ny, nz = shape
+    say(f"one step fp64 {name} {shape}")
+    f0 = random_populations((nz, ny, nx), seed=zlib.crc32(name.encode()) % 1000)
+    body = (1e-5, -2e-5, 5e-6)
+    kw = dict(faces=faces, u_in=(0.05, 0.0, 0.0), body=body, s_bulk=1.2, s_high=(0.9, 1.1, 1.3, 0.8))
+    prof = _inlet(ny, nz) if profile else None
+    S = O.OracleSim(nx, ny, nz, 0.02, faces=faces, u_in=kw["u_in"], body=body, s_bulk=1.2, s_high=kw["s_high"])
+    if prof is not None:
+        S.set_inlet_profile(prof)
+    S.set_state(f0)
+    S.step(1)
+    ref = S.get_state()
+    s = gpu_solver(nx, ny, nz, 0.02, storage="f64", inlet_profile=prof, **kw)
+    s.set_populations(f0)
+    s.step(1)
+    got = to_np(s.get_populations())
+    err = np.abs(got - ref).max()
+    say(f"  max |diff| = {err:.3e}")
+    assert err < 1e-14
+
+
+@pytest.mark.parametrize("name,shape,faces,profile", FACE_CASES[:5], ids=[c[0] for c in FACE_CASES[:5]])
+def test_fifty_steps_fp32(name, shape, faces, profile):
+    nx, ny, nz = shape
+    say(f"fifty steps fp32 {name} {shape}")
+    f0 = random_populations((nz, ny, nx), seed=zlib.crc32(name.encode()) % 1000, amp=0.01).astype(np.float32).astype(np.float64)
+    kw = dict(faces=faces, u_in=(0.05, 0.0, 0.0), s_bulk=1.0, s_high=(1.0, 1.0, 1.0, 1.0))
+    prof = _inlet(ny, nz) if profile else None
+    S = O.OracleSim(nx, ny, nz, 0.02, faces=faces, u_in=kw["u_in"])
+    if prof is not None:
+        S.set_inlet_profile(prof)
+    S.set_state(f0)
+    S.step(50)
+    r_ref, u_ref = S.macros()
+    s = gpu_solver(nx, ny, nz, 0.02, storage="f32", inlet_profile=prof, **kw)
+    s.set_populations(f0)
+    s.step(50)
+    r, u = (to_np(t) for t in s.macros())
+    e_u, e_r = rel_l2(u, u_ref), rel_l2(r, r_ref)
+    say(f"  rel-L2 u={e_u:.3e} rho={e_r:.3e}")
+    assert e_u <= FP32_GATE and e_r <= FP32_GATE
+
+
+# ---------------------------------------------------------------------------
+# immersed boundary: maps bit-exact, fields to round-off (FP64) and gate (FP32)
+# ---------------------------------------------------------------------------
+def _ib_scene(nx, ny, nz, seed):
+    rng = np.random.default_rng(seed)
+    sph = synth.fibonacci_sphere(400, 5.0, (12.3, ny / 2 + 0.2, nz / 2 - 0.1))
+    box = synth.random_box(2000, (26.0, 6.0, 5.0), (32.0, 12.0, 11.0), seed + 1)  # many samples per cell
+    on_nodes = np.array([[20.0, 21.0, 30.5], [4.0, 5.0, 6.0], [3.0, 3.0, 8.0]], np.float32)
+    xyz = np.concatenate([sph, box, on_nodes], axis=1)
+    n = xyz.shape[1]
+    ub = (0.01 * rng.standard_normal((3, n))).astype(np.float32)
+    # area per sample ~ surface (or volume) per sample, so that the summed
+    # a_s gamma_s per cell stays O(1) (explicit penalty forcing)
+    area = np.concatenate([np.full(400, 4 * np.pi * 25.0 / 400), np.full(2000, 216.0 / 2000), np.ones(3)])
+    area = (area * (0.7 + 0.6 * rng.random(n))).astype(np.float32)
+    gain = (0.5 + rng.random(n)).astype(np.float32)
+    return xyz, ub, area, gain
+
+
+IB_CASES = [
+    ("periodic", (70, 18, 16), (P, P, P, P, P, P)),
+    ("inlet-outflow-walls", (70, 18, 16), (IN, OUT, NS, FS, P, P)),
+]
+
+
+@pytest.mark.parametrize("name,shape,faces", IB_CASES, ids=[c[0] for c in IB_CASES])
+def test_ib_maps_bit_exact(name, shape, faces):
+    nx, ny, nz = shape
+    say(f"ib maps {name}")
+    xyz, ub, area, gain = _ib_scene(nx, ny, nz, 7)
+    S = O.OracleSim(nx, ny, nz, 0.05, faces=faces)
+    S.set_markers(xyz, ub.astype(np.float64), area.astype(np.float64), gain.astype(np.float64))
+    fl_ref, cell_ref, perm_ref = S.maps()
+    s = gpu_solver(nx, ny, nz, 0.05, faces=faces, u_in=(0.03, 0, 0))
+    s.set_solids(xyz, ub, area, gain)
+    fl, cell, perm = (t.cpu().numpy() for t in s.solid_maps())
+    assert np.array_equal(cell, cell_ref)
+    assert np.array_equal(perm, perm_ref)
+    assert np.array_equal(fl, fl_ref)
+
+
+@pytest.mark.parametrize("name,shape,faces", IB_CASES, ids=[c[0] for c in IB_CASES])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_ib_steps(name, shape, faces, storage):
+    nx, ny, nz = shape
+    say(f"ib steps {name} {storage}")
+    xyz, ub, area, gain = _ib_scene(nx, ny, nz, 7)
+    rng = np.random.default_rng(3)
+    rho = (1.0 + 1e-3 * rng.standard_normal((nz, ny, nx))).astype(np.float32)
+    u = np.zeros((3, nz, ny, nx), np.float32)
+    u[0] = 0.03
+    u += (0.005 * rng.standard_normal(u.shape)).astype(np.float32)
+    steps = 20
+    S = O.OracleSim(nx, ny, nz, 0.05, faces=faces, u_in=(0.03, 0, 0))
+    S.set_markers(xyz, ub.astype(np.float64), area.astype(np.float64), gain.astype(np.float64))
+    S.init_equilibrium(rho.astype(np.float64), u.astype(np.float64))
+    S.step(steps)
+    r_ref, u_ref = S.macros()
+    F_ref = S.last_force()
+    s = gpu_solver(nx, ny, nz, 0.05, storage=storage, faces=faces, u_in=(0.03, 0, 0))
+    s.set_solids(xyz, ub, area, gain)
+    real = np.float64 if storage == "f64" else np.float32
+    s.init_equilibrium(rho.astype(real), u.astype(real))
+    s.step(steps)
+    r, uu = (to_np(t) for t in s.macros())
+    F = s.ib_force()
+    e_u, e_r, e_F = rel_l2(uu, u_ref), rel_l2(r, r_ref), rel_l2(F, F_ref)
+    say(f"  rel-L2 u={e_u:.3e} rho={e_r:.3e} force={e_F:.3e}")
+    gate = 1e-12 if storage == "f64" else FP32_GATE
+    assert e_u <= gate and e_r <= gate and e_F <= (1e-11 if storage == "f64" else 1e-4)
+
+
+def test_ib_force_eval_matches_oracle():
+    nx, ny, nz = 70, 18, 16
+    say("ib force eval")
+    xyz, ub, area, gain = _ib_scene(nx, ny, nz, 11)
+    f0 = random_populations((nz, ny, nx), seed=12, amp=0.01)
+    S = O.OracleSim(nx, ny, nz, 0.05)
+    S.set_markers(xyz, ub.astype(np.float64), area.astype(np.float64), gain.astype(np.float64))
+    S.set_state(f0)
+    ref = S.ib_force()
+    s = gpu_solver(nx, ny, nz, 0.05, storage="f64")
+    s.set_solids(xyz, ub, area, gain)
+    s.set_populations(f0)
+    got = s.ib_force_eval()
+    assert rel_l2(got, ref) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# state handling and error paths
+# ---------------------------------------------------------------------------
+def test_checkpoint_restore_is_bitwise():
+    say("checkpoint/restore")
+    rho, u = synth.taylor_green(32, 0.05, kind="3d", dtype=np.float32)
+    s = gpu_solver(32, 32, 32, 0.01, storage="f16")
+    s.init_equilibrium(rho, u)
+    s.step(3)
+    snap = s.checkpoint()
+    s.step(5)
+    a = s.get_populations().clone()
+    s.restore(snap)
+    s.step(5)
+    b = s.get_populations()
+    assert torch.equal(a, b)
+
+
+def test_nonfinite_state_reported():
+    say("non-finite detection")
+    from paper_2101_11856_amd import lbm
+    f0 = random_populations((6, 5, 9), seed=1)
+    f0[3, 2, 1, 4] = np.nan
+    s = gpu_solver(9, 5, 6, 0.1)
+    s.set_populations(f0.astype(np.float32))
+    with pytest.raises(lbm.LbmError) as e:
+        s.conserved()
+    assert e.value.status == 4
+
+
+def test_markers_outside_domain_rejected():
+    say("marker validation")
+    from paper_2101_11856_amd import lbm
+    s = gpu_solver(16, 8, 8, 0.1, faces=(IN, OUT, NS, NS, P, P), u_in=(0.02, 0, 0))
+    with pytest.raises(lbm.LbmError) as e:
+        s.set_solids(np.array([[3.0], [7.5], [2.0]], np.float32))  # stencil crosses the +y wall
+    assert e.value.status == 1
+    s.set_solids(np.array([[3.0], [6.5], [2.0]], np.float32))
+    s.set_solids(None)  # empty set
+    s.step(2)
+
+
+def test_empty_and_single_cell_cases():
+    say("degenerate grids")
+    s = gpu_solver(1, 1, 1, 0.1)
+    s.init_equilibrium(np.ones((1, 1, 1), np.float32), np.zeros((3, 1, 1, 1), np.float32))
+    s.step(3)
+    r, u = s.macros()
+    assert abs(float(r.item()) - 1.0) < 1e-7 and float(u.abs().max()) < 1e-7
+    s.step(0)
