@@ -126,6 +126,9 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid edge of the turbulence workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the 16-bit and sphere runs")
+    ap.add_argument("--storage", default="f32", help="population storage of --profile-pass")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="profiler pass: the workload only, then 3 state copies of known size (calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -143,6 +146,18 @@ def main():
     log(f"generating turbulence field {n}^3")
     rho, u = synth.turbulence(n)
     cells = n ** 3
+
+    if args.profile_pass:
+        s = turbulence_solver(n, args.storage, rho, u)
+        t = timed_steps(s, args.steps, args.warmup)
+        snap = s.checkpoint()
+        for _ in range(3):
+            s.checkpoint(snap)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_pass": True, "storage": args.storage, "n": n, "steps": args.steps,
+                          "ms_per_step": 1e3 * t / args.steps, "copy_bytes_each_way": s.state_bytes(),
+                          "kernel_source_sha256_16": kernel_hash()}), flush=True)
+        return
 
     log("fp32 run")
     s = turbulence_solver(n, "f32", rho, u)

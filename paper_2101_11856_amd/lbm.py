@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm.so")
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 
 PERIODIC, NOSLIP, FREESLIP, INLET, OUTFLOW = 0, 1, 2, 3, 4
 F32, F16DEV, BF16DEV, F64 = 0, 1, 2, 3
