@@ -90,10 +90,32 @@ template <> struct Store<LBM_BF16DEV> {
 // geometry shared by every kernel
 // ---------------------------------------------------------------------------
 
+// Build-time tuning switches (measured; see the design notes for the values).
+#ifndef LBM_NT_LOADS
+#define LBM_NT_LOADS 0      // population reads with the non-temporal (streaming) hint
+#endif
+#ifndef LBM_WAVES
+#define LBM_WAVES 4         // wavefronts per workgroup of the fused kernel
+#endif
+#ifndef LBM_XCD_REMAP
+#define LBM_XCD_REMAP 0     // contiguous logical blocks per XCD (off: all XCDs share one moving front)
+#endif
+
 // Work item = one x-segment of 64 nodes of one (y, z) row; a wavefront owns
-// one work item, a 256-thread workgroup four consecutive ones.
+// one work item, a workgroup LBM_WAVES consecutive ones.
 constexpr int SEG = 64;
-constexpr int WAVES_PER_BLOCK = 4;
+constexpr int WAVES_PER_BLOCK = LBM_WAVES;
+
+// streaming read of a population (used once per step, except the one-element
+// overlap of neighbouring segments, which the L2 still catches)
+template <typename T> __device__ __forceinline__ T ld_stream(const T *p)
+{
+#if LBM_NT_LOADS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 
 struct Geom {
     int nx, ny, nz;
@@ -104,11 +126,17 @@ struct Geom {
     int face[6];
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of logical blocks so that the x-neighbouring segments of a
-// row (which share cache lines at their edges) land in the same L2.
+// Workgroups are dispatched round-robin over the 8 XCDs.  The remap gives each
+// XCD a contiguous range of logical blocks, so that x-neighbouring segments
+// (which share cache lines at their edges) land in the same L2.  Measured on
+// MI355X it is slower (23.1 vs 25.8 GLUPS at 256^3 FP32): with plain dispatch
+// order all XCDs stream through one narrow front of the domain, which keeps
+// DRAM pages open, and the shared edge lines are caught by the Infinity Cache.
 __device__ __forceinline__ int xcd_remap(int bid, int nb)
 {
+#if !LBM_XCD_REMAP
+    return bid;
+#endif
     const int xcd = bid & 7, local = bid >> 3;
     const int per = nb >> 3, rem = nb & 7;
     return xcd * per + (xcd < rem ? xcd : rem) + local;
@@ -209,7 +237,7 @@ __device__ __forceinline__ R pull_one(int i, const typename Store<ST>::T *__rest
 {
     const PullSrc s = resolve(i, x, y, z, g);
     const int64_t idx = (int64_t)s.pl * g.plane + ((int64_t)s.sz * g.ny + s.sy) * g.nxp + s.sx;
-    R v = Store<ST>::dec(in[idx]);
+    R v = Store<ST>::dec(ld_stream(in + idx));
     if (s.inlet) {
         const R cu = (R)CX[i] * inl.at(0, s.sy, s.sz, g.ny, g.nz) + (R)CY[i] * inl.at(1, s.sy, s.sz, g.ny, g.nz) +
                      (R)CZ[i] * inl.at(2, s.sy, s.sz, g.ny, g.nz);
@@ -251,7 +279,7 @@ __device__ __forceinline__ void pull_interior(R (&f)[3][3][3], const typename St
     for (int i = 0; i < Q; ++i) {
         const int row = (zs[CZ[i] + 1] * g.ny + ys[CY[i] + 1]) * g.nxp;
         const typename Store<ST>::T *pl = in + (int64_t)i * g.plane + row;
-        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(pl[xs[CX[i] + 1]]);
+        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(ld_stream(pl + xs[CX[i] + 1]));
     }
 }
 

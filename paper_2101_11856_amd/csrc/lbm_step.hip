@@ -68,7 +68,7 @@ __device__ __forceinline__ void scalar_update(const StepParams<ST> &P, int x, in
 // fused step
 // ---------------------------------------------------------------------------
 template <int ST, bool BAND, bool SCALAR>
-__global__ void __launch_bounds__(256) k_fused(const StepParams<ST> P)
+__global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams<ST> P)
 {
     using R = typename Store<ST>::R;
     const Geom &g = P.g;
@@ -278,7 +278,7 @@ template <int ST> static hipError_t fused_st(lbm_ctx *c)
 {
     const StepParams<ST> P = make_params<ST>(c);
     const bool band = c->nm > 0, scalar = c->p.passive_scalar != 0;
-    const dim3 grid(blocks_for_items(c->g.W)), block(256);
+    const dim3 grid(blocks_for_items(c->g.W)), block(SEG * WAVES_PER_BLOCK);
     if (band && scalar) hipLaunchKernelGGL((k_fused<ST, true, true>), grid, block, 0, c->stream, P);
     else if (band) hipLaunchKernelGGL((k_fused<ST, true, false>), grid, block, 0, c->stream, P);
     else if (scalar) hipLaunchKernelGGL((k_fused<ST, false, true>), grid, block, 0, c->stream, P);
