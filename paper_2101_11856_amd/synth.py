@@ -9,7 +9,7 @@ Arrays use the library's layout: scalar fields [nz, ny, nx] (x fastest),
 vector fields [3, nz, ny, nx], marker arrays [3, n] (float32 positions in
 lattice units, a node sits at integer coordinates).
 
-The paper's scenes (Sec. 6, Table 3) use meshes and smoke that are not
+The paper's scenes (Sec. 5, Table 3) use meshes and smoke that are not
 available; these generators stand in for them:
   * Taylor-Green vortex (32^3 parity case),
   * decaying turbulence with an E(k) ~ k^-5/3 spectrum (256^3 throughput case),
