@@ -167,6 +167,51 @@ lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
 lbm_status lbm_checkpoint(lbm_ctx *ctx, void *dst);
 lbm_status lbm_restore(lbm_ctx *ctx, const void *src);
 
+/* Replace the penalty gains gamma_s of the current samples (device float[n],
+ * input order) without re-sorting.  Async. */
+lbm_status lbm_set_gains(lbm_ctx *ctx, const float *gain);
+
+/* ---- adjoint (reverse mode of lbm_step) ----------------------------------
+ * The adjoint state lambda = dJ/df has the layout of the populations, in the
+ * arithmetic type (float, double for LBM_F64), and lives in a caller-owned
+ * adjoint workspace.  Gradients accumulate in FP64.  Reading of the paper: the
+ * objective depends on the final state only (drag from lbm_ib_force_eval,
+ * velocities from lbm_macros), so the reverse sweep starts from seeds on that
+ * state and walks the steps backwards over a tape of forward states. */
+
+/* Device bytes of the adjoint workspace for the current grid and samples. */
+lbm_status lbm_adjoint_ws_size(const lbm_ctx *ctx, size_t *bytes);
+
+/* Bind the adjoint workspace (device, 256-byte aligned) and set lambda = 0.
+ * Must be called again after lbm_set_solids.  Async. */
+lbm_status lbm_adjoint_init(lbm_ctx *ctx, void *adj_ws, size_t bytes);
+
+/* lambda += (d(rho, u0)/df)^T (g_rho, g_u) for the lbm_macros outputs of the
+ * current state (Eq. 2 after the pull).  g_rho: device real[N] or NULL;
+ * g_u: device real[3][N] or NULL; g_inlet: device double[3][nz][ny] (+=) for
+ * dJ/du_in, or NULL.  Async. */
+lbm_status lbm_adjoint_seed_macros(lbm_ctx *ctx, const void *g_rho, const void *g_u, double *g_inlet);
+
+/* lambda += (dF/df)^T g_force for the penalty force F = lbm_ib_force_eval of
+ * the current state (Eqs. 6-8); g_gain: device double[n] (+=, input order)
+ * receives dF/dgamma . g_force, or NULL.  Async. */
+lbm_status lbm_adjoint_seed_force(lbm_ctx *ctx, const double g_force[3], double *g_inlet, double *g_gain);
+
+/* Advance nsteps forward (as lbm_step), first copying the state before each
+ * step into tape + k * lbm_state_bytes (device, caller-owned).  Async. */
+lbm_status lbm_record_tape(lbm_ctx *ctx, int32_t nsteps, void *tape);
+
+/* Reverse sweep over a tape of nsteps forward states (as written by
+ * lbm_record_tape): for k = nsteps-1 .. 0, lambda <- (df(k+1)/df(k))^T lambda,
+ * with f(k) read from the tape.  g_inlet (double[3][nz][ny]) and g_gain
+ * (double[n], input order) accumulate dJ/du_in and dJ/dgamma; either may be
+ * NULL.  The context's own population state is not touched.  Async. */
+lbm_status lbm_adjoint_step(lbm_ctx *ctx, int32_t nsteps, const void *tape, double *g_inlet, double *g_gain);
+
+/* lambda out of / into a dense device real[27][N] array.  Async. */
+lbm_status lbm_adjoint_get(lbm_ctx *ctx, void *lambda);
+lbm_status lbm_adjoint_set(lbm_ctx *ctx, const void *lambda);
+
 /* Release the host-side context (the workspaces stay with the caller). */
 void lbm_destroy(lbm_ctx *ctx);
 

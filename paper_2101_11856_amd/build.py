@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_step.hip", "lbm_aux.hip", "lbm_api.hip"]
+SOURCES = ["lbm_step.hip", "lbm_aux.hip", "lbm_adjoint.hip", "lbm_api.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -322,7 +322,7 @@ lbm_status lbm_step(lbm_ctx *c, int32_t nsteps)
     CHECK_CTX(c);
     if (nsteps < 0) return fail(c, LBM_E_INVAL, "nsteps must be >= 0");
     for (int32_t t = 0; t < nsteps; ++t) {
-        if (c->nm > 0) HIP_TRY(c, launch_band_ib(c, c->ftot), "lbm_step (immersed boundary)");
+        if (c->nm > 0) HIP_TRY(c, launch_band_ib(c, c->fA, c->ftot), "lbm_step (immersed boundary)");
         HIP_TRY(c, launch_fused(c), "lbm_step (fused)");
         std::swap(c->fA, c->fB);
         std::swap(c->scA, c->scB);
@@ -368,7 +368,7 @@ lbm_status lbm_ib_force_eval(lbm_ctx *c, double out[3])
         out[0] = out[1] = out[2] = 0.0;
         return LBM_OK;
     }
-    HIP_TRY(c, launch_band_ib(c, c->ftot_eval), "lbm_ib_force_eval");
+    HIP_TRY(c, launch_band_ib(c, c->fA, c->ftot_eval), "lbm_ib_force_eval");
     HIP_TRY(c, hipMemcpyAsync(out, c->ftot_eval, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
             "lbm_ib_force_eval");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "lbm_ib_force_eval");
@@ -410,6 +410,110 @@ lbm_status lbm_restore(lbm_ctx *c, const void *src)
     if (c->p.passive_scalar)
         HIP_TRY(c, launch_copy(c, c->scA, static_cast<const char *>(src) + fb, (size_t)c->rows * c->g.nxp * 4),
                 "lbm_restore");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_gains(lbm_ctx *c, const float *gain)
+{
+    CHECK_CTX(c);
+    if (c->nm == 0) return fail(c, LBM_E_STATE, "no samples are set");
+    if (!gain) return fail(c, LBM_E_INVAL, "gain is NULL");
+    HIP_TRY(c, launch_set_gains(c, gain), "lbm_set_gains");
+    return LBM_OK;
+}
+
+lbm_status lbm_record_tape(lbm_ctx *c, int32_t nsteps, void *tape)
+{
+    CHECK_CTX(c);
+    if (nsteps < 0) return fail(c, LBM_E_INVAL, "nsteps must be >= 0");
+    if (nsteps > 0 && !tape) return fail(c, LBM_E_INVAL, "tape is NULL");
+    const size_t sb = state_bytes(c);
+    for (int32_t k = 0; k < nsteps; ++k) {
+        const lbm_status s = lbm_checkpoint(c, static_cast<char *>(tape) + (size_t)k * sb);
+        if (s != LBM_OK) return s;
+        const lbm_status t = lbm_step(c, 1);
+        if (t != LBM_OK) return t;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_ws_size(const lbm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return fail(const_cast<lbm_ctx *>(c), LBM_E_INVAL, "NULL argument");
+    *bytes = adjoint_ws_bytes(c);
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_init(lbm_ctx *c, void *adj_ws, size_t bytes)
+{
+    CHECK_CTX(c);
+    if (!adj_ws || reinterpret_cast<uintptr_t>(adj_ws) % ALIGN)
+        return fail(c, LBM_E_INVAL, "adjoint workspace must be non-NULL and 256-byte aligned");
+    if (bytes < adjoint_ws_bytes(c))
+        return fail(c, LBM_E_NOMEM, "adjoint workspace too small: need " + std::to_string(adjoint_ws_bytes(c)) + " bytes");
+    adjoint_bind(c, adj_ws, bytes);
+    HIP_TRY(c, launch_zero(c, c->lam_in, (size_t)Q * c->g.plane * c->rsize), "lbm_adjoint_init");
+    return LBM_OK;
+}
+
+static lbm_status adjoint_ready(lbm_ctx *c)
+{
+    if (!c->aws) return fail(c, LBM_E_STATE, "lbm_adjoint_init has not been called");
+    if (c->nm > 0 && c->nband > c->adj_band_cap)
+        return fail(c, LBM_E_STATE, "samples changed after lbm_adjoint_init; call it again");
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_seed_macros(lbm_ctx *c, const void *g_rho, const void *g_u, double *g_inlet)
+{
+    CHECK_CTX(c);
+    const lbm_status s = adjoint_ready(c);
+    if (s != LBM_OK) return s;
+    HIP_TRY(c, adjoint_seed_macros(c, g_rho, g_u, g_inlet), "lbm_adjoint_seed_macros");
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_seed_force(lbm_ctx *c, const double g_force[3], double *g_inlet, double *g_gain)
+{
+    CHECK_CTX(c);
+    const lbm_status s = adjoint_ready(c);
+    if (s != LBM_OK) return s;
+    if (!g_force) return fail(c, LBM_E_INVAL, "g_force is NULL");
+    HIP_TRY(c, adjoint_seed_force(c, g_force, g_inlet, g_gain), "lbm_adjoint_seed_force");
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx *c, int32_t nsteps, const void *tape, double *g_inlet, double *g_gain)
+{
+    CHECK_CTX(c);
+    const lbm_status s = adjoint_ready(c);
+    if (s != LBM_OK) return s;
+    if (nsteps < 0) return fail(c, LBM_E_INVAL, "nsteps must be >= 0");
+    if (nsteps > 0 && !tape) return fail(c, LBM_E_INVAL, "tape is NULL");
+    const size_t sb = state_bytes(c);
+    for (int32_t k = nsteps - 1; k >= 0; --k)
+        HIP_TRY(c, adjoint_step_one(c, static_cast<const char *>(tape) + (size_t)k * sb, g_inlet, g_gain),
+                "lbm_adjoint_step");
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_get(lbm_ctx *c, void *lambda)
+{
+    CHECK_CTX(c);
+    const lbm_status s = adjoint_ready(c);
+    if (s != LBM_OK) return s;
+    if (!lambda) return fail(c, LBM_E_INVAL, "lambda is NULL");
+    HIP_TRY(c, adjoint_io(c, lambda, false), "lbm_adjoint_get");
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_set(lbm_ctx *c, const void *lambda)
+{
+    CHECK_CTX(c);
+    const lbm_status s = adjoint_ready(c);
+    if (s != LBM_OK) return s;
+    if (!lambda) return fail(c, LBM_E_INVAL, "lambda is NULL");
+    HIP_TRY(c, adjoint_io(c, const_cast<void *>(lambda), true), "lbm_adjoint_set");
     return LBM_OK;
 }
 

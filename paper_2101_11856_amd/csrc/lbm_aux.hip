@@ -559,6 +559,19 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
     return hipStreamSynchronize(st);
 }
 
+__global__ void k_gather_gain(int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ gain,
+                              float *__restrict__ gain_s)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) gain_s[k] = gain[perm[k]];
+}
+
+hipError_t launch_set_gains(lbm_ctx *c, const float *gain)
+{
+    hipLaunchKernelGGL(k_gather_gain, grid_for(c->nm), dim3(256), 0, c->stream, c->nm, c->m_perm, gain, c->m_gain);
+    return hipGetLastError();
+}
+
 hipError_t launch_solid_maps(lbm_ctx *c, uint8_t *flags, int32_t *cell, int32_t *perm)
 {
     const MarkerGeom mg = marker_geom(c);

@@ -46,6 +46,13 @@ struct lbm_ctx {
     int32_t *band_cell = nullptr;  // [nband]
     void *band_ru = nullptr;       // [nband] real4 (rho, u)
     void *band_force = nullptr;    // [nband] real4 (g, 0)
+    // adjoint workspace (caller-owned)
+    char *aws = nullptr;
+    size_t aws_bytes = 0;
+    int64_t adj_band_cap = -1;     // band capacity the adjoint workspace was sized for (-1 = unbound)
+    void *lam_in = nullptr, *lam_out = nullptr, *adjM = nullptr;  // real planes like the populations
+    void *band_phi = nullptr;      // [nband] real4 adjoint of the band force
+    void *band_bar = nullptr;      // [nband] real4 adjoint of (rho, u0) at band nodes
     std::string err;
 };
 
@@ -61,7 +68,7 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L);
 
 // launchers (return the first HIP error)
 hipError_t launch_fused(lbm_ctx *c);
-hipError_t launch_band_ib(lbm_ctx *c, double *ftot);  // band pull + interpolation/spreading of the current state
+hipError_t launch_band_ib(lbm_ctx *c, const void *state, double *ftot);  // band pull + interpolation/spreading of `state`
 hipError_t launch_init_eq(lbm_ctx *c, const void *rho, const void *u);
 hipError_t launch_set_pop(lbm_ctx *c, const void *f);
 hipError_t launch_get_pop(lbm_ctx *c, void *f);
@@ -73,5 +80,14 @@ hipError_t launch_scalar_io(lbm_ctx *c, float *dst, const float *src, bool to_st
 hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area, const float *gain,
                         int *bad_count_host);
 hipError_t launch_solid_maps(lbm_ctx *c, uint8_t *flags, int32_t *cell, int32_t *perm);
+hipError_t launch_set_gains(lbm_ctx *c, const float *gain);
+
+// adjoint (lbm_adjoint.hip)
+size_t adjoint_ws_bytes(const lbm_ctx *c);
+void adjoint_bind(lbm_ctx *c, void *ws, size_t bytes);
+hipError_t adjoint_step_one(lbm_ctx *c, const void *state, double *g_inlet, double *g_gain);
+hipError_t adjoint_seed_macros(lbm_ctx *c, const void *g_rho, const void *g_u, double *g_inlet);
+hipError_t adjoint_seed_force(lbm_ctx *c, const double g_force[3], double *g_inlet, double *g_gain);
+hipError_t adjoint_io(lbm_ctx *c, void *dense, bool to_state);
 
 }  // namespace lbm

@@ -292,7 +292,7 @@ template <typename R> struct Rates {
 };
 
 // Raw moments along one axis of the line (v(-1), v(0), v(+1)) -> (m0, m1, m2).
-template <typename R> __device__ __forceinline__ void raw3(R &a, R &b, R &c)
+template <typename R> __host__ __device__ __forceinline__ void raw3(R &a, R &b, R &c)
 {
     const R s = c + a, t = c - a;
     a = s + b;
@@ -300,21 +300,21 @@ template <typename R> __device__ __forceinline__ void raw3(R &a, R &b, R &c)
     c = s;
 }
 // Central shift along one axis: (m0, m1, m2) -> (k0, k1, k2) about u.
-template <typename R> __device__ __forceinline__ void shift3(R &m0, R &m1, R &m2, R u)
+template <typename R> __host__ __device__ __forceinline__ void shift3(R &m0, R &m1, R &m2, R u)
 {
     const R k1 = m1 - u * m0;
     m2 = m2 - u * (m1 + k1);
     m1 = k1;
 }
 // Inverse shift: (k0, k1, k2) -> (m0, m1, m2).
-template <typename R> __device__ __forceinline__ void unshift3(R &k0, R &k1, R &k2, R u)
+template <typename R> __host__ __device__ __forceinline__ void unshift3(R &k0, R &k1, R &k2, R u)
 {
     const R m1 = k1 + u * k0;
     k2 = k2 + u * (k1 + m1);
     k1 = m1;
 }
 // Inverse raw transform: (m0, m1, m2) -> (v(-1), v(0), v(+1)).
-template <typename R> __device__ __forceinline__ void iraw3(R &a, R &b, R &c)
+template <typename R> __host__ __device__ __forceinline__ void iraw3(R &a, R &b, R &c)
 {
     const R h = (R)0.5 * c;
     const R m0 = a, m1 = b, m2 = c;
@@ -324,21 +324,21 @@ template <typename R> __device__ __forceinline__ void iraw3(R &a, R &b, R &c)
 }
 
 // Apply a 3-point line operation to the 9 lines of f[z][y][x] along x, y or z.
-template <typename R, typename Op> __device__ __forceinline__ void lines_x(R (&f)[3][3][3], Op op)
+template <typename R, typename Op> __host__ __device__ __forceinline__ void lines_x(R (&f)[3][3][3], Op op)
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) op(f[a][b][0], f[a][b][1], f[a][b][2]);
 }
-template <typename R, typename Op> __device__ __forceinline__ void lines_y(R (&f)[3][3][3], Op op)
+template <typename R, typename Op> __host__ __device__ __forceinline__ void lines_y(R (&f)[3][3][3], Op op)
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) op(f[a][0][b], f[a][1][b], f[a][2][b]);
 }
-template <typename R, typename Op> __device__ __forceinline__ void lines_z(R (&f)[3][3][3], Op op)
+template <typename R, typename Op> __host__ __device__ __forceinline__ void lines_z(R (&f)[3][3][3], Op op)
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -351,35 +351,15 @@ template <typename R> struct Macro {
     R drho, jx, jy, jz;
 };
 
-// f holds the pulled deviations; on return f holds the post-collision
-// deviations and (rho, u) the density and half-force velocity used.
+// Relaxation of the central moments of d (index [c][b][a] = exponents
+// (a,b,c)) at density 1 + drho, half-force velocity u and force F:
+// kappa'(d) = kappa(d) - S (kappa(d) + Delta) + (I - S/2) kappa_F, where
+// Delta = kappa(w; u) - kappa_eq(rho) is written out so that no large terms
+// cancel (kappa - kappa_eq = kappa(d) + Delta).
 template <typename R>
-__device__ __forceinline__ void collide(R (&f)[3][3][3], R Fx, R Fy, R Fz, const Rates<R> &rt, R &rho_o, R &ux_o,
-                                        R &uy_o, R &uz_o)
+__host__ __device__ __forceinline__ void relax(R (&f)[3][3][3], R ux, R uy, R uz, R drho, R Fx, R Fy, R Fz, const Rates<R> &rt)
 {
     const R third = (R)(1.0 / 3.0), ninth = (R)(1.0 / 9.0), t27 = (R)(1.0 / 27.0);
-    // raw moments of d (index [mz][my][mx])
-    auto raw = [](R &a, R &b, R &c) { raw3(a, b, c); };
-    lines_x(f, raw);
-    lines_y(f, raw);
-    lines_z(f, raw);
-    const R drho = f[0][0][0];
-    const R rho = (R)1 + drho;
-    const R inv = (R)1 / rho;
-    const R ux = (f[0][0][1] + (R)0.5 * Fx) * inv;
-    const R uy = (f[0][1][0] + (R)0.5 * Fy) * inv;
-    const R uz = (f[1][0][0] + (R)0.5 * Fz) * inv;
-    rho_o = rho;
-    ux_o = ux;
-    uy_o = uy;
-    uz_o = uz;
-    // central moments of d about u
-    lines_x(f, [ux](R &a, R &b, R &c) { shift3(a, b, c, ux); });
-    lines_y(f, [uy](R &a, R &b, R &c) { shift3(a, b, c, uy); });
-    lines_z(f, [uz](R &a, R &b, R &c) { shift3(a, b, c, uz); });
-
-    // Delta = kappa(w; u) - kappa_eq(rho): equilibrium offsets written so that
-    // no large terms cancel.  kappa - kappa_eq = kappa(d) + Delta.
     const R x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
     const R px = third + x2, py = third + y2, pz = third + z2;
     const R dr3 = drho * third, dr9 = drho * ninth;
@@ -432,6 +412,45 @@ __device__ __forceinline__ void collide(R (&f)[3][3][3], R Fx, R Fy, R Fz, const
         const R d6 = (x2 * y2 + x2 * z2 + y2 * z2) * third + (x2 + y2 + z2) * ninth + x2 * y2 * z2 - drho * t27;
         f[2][2][2] -= rt.s6 * (f[2][2][2] + d6);
     }
+}
+
+template <typename R> __host__ __device__ __forceinline__ void raw_all(R (&f)[3][3][3])
+{
+    auto raw = [](R &a, R &b, R &c) { raw3(a, b, c); };
+    lines_x(f, raw);
+    lines_y(f, raw);
+    lines_z(f, raw);
+}
+
+// Half-force velocity and density from raw moments of d.
+template <typename R>
+__host__ __device__ __forceinline__ void velocity(const R (&m)[3][3][3], R Fx, R Fy, R Fz, R &drho, R &ux, R &uy, R &uz)
+{
+    drho = m[0][0][0];
+    const R inv = (R)1 / ((R)1 + drho);
+    ux = (m[0][0][1] + (R)0.5 * Fx) * inv;
+    uy = (m[0][1][0] + (R)0.5 * Fy) * inv;
+    uz = (m[1][0][0] + (R)0.5 * Fz) * inv;
+}
+
+// f holds the pulled deviations; on return f holds the post-collision
+// deviations and (rho, u) the density and half-force velocity used.
+template <typename R>
+__host__ __device__ __forceinline__ void collide(R (&f)[3][3][3], R Fx, R Fy, R Fz, const Rates<R> &rt, R &rho_o, R &ux_o,
+                                        R &uy_o, R &uz_o)
+{
+    raw_all(f);  // raw moments of d (index [mz][my][mx])
+    R drho, ux, uy, uz;
+    velocity(f, Fx, Fy, Fz, drho, ux, uy, uz);
+    rho_o = (R)1 + drho;
+    ux_o = ux;
+    uy_o = uy;
+    uz_o = uz;
+    // central moments of d about u
+    lines_x(f, [ux](R &a, R &b, R &c) { shift3(a, b, c, ux); });
+    lines_y(f, [uy](R &a, R &b, R &c) { shift3(a, b, c, uy); });
+    lines_z(f, [uz](R &a, R &b, R &c) { shift3(a, b, c, uz); });
+    relax(f, ux, uy, uz, drho, Fx, Fy, Fz, rt);
     // back to raw moments, then to populations
     lines_z(f, [uz](R &a, R &b, R &c) { unshift3(a, b, c, uz); });
     lines_y(f, [uy](R &a, R &b, R &c) { unshift3(a, b, c, uy); });

@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(256) k_ib(const IbParams<R> P)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int ST> static StepParams<ST> make_params(lbm_ctx *c)
+template <int ST> StepParams<ST> make_params(lbm_ctx *c)
 {
     using R = typename Store<ST>::R;
     using T = typename Store<ST>::T;
@@ -297,11 +297,12 @@ hipError_t launch_fused(lbm_ctx *c)
     return hipErrorInvalidValue;
 }
 
-template <int ST> static hipError_t band_ib_st(lbm_ctx *c, double *ftot)
+template <int ST> static hipError_t band_ib_st(lbm_ctx *c, const void *state, double *ftot)
 {
     using R = typename Store<ST>::R;
     using R4 = typename StepParams<ST>::R4;
-    const StepParams<ST> P = make_params<ST>(c);
+    StepParams<ST> P = make_params<ST>(c);
+    P.fin = static_cast<const typename Store<ST>::T *>(state);
     const unsigned nb = (unsigned)((c->nband + 255) / 256);
     hipLaunchKernelGGL((k_band<ST>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, P, c->band_cell, c->nband,
                        static_cast<R4 *>(c->band_ru), static_cast<R4 *>(c->band_force), ftot);
@@ -321,14 +322,14 @@ template <int ST> static hipError_t band_ib_st(lbm_ctx *c, double *ftot)
     return hipGetLastError();
 }
 
-hipError_t launch_band_ib(lbm_ctx *c, double *ftot)
+hipError_t launch_band_ib(lbm_ctx *c, const void *state, double *ftot)
 {
     if (c->nm <= 0) return hipSuccess;
     switch (c->p.storage) {
-    case LBM_F32: return band_ib_st<LBM_F32>(c, ftot);
-    case LBM_F16DEV: return band_ib_st<LBM_F16DEV>(c, ftot);
-    case LBM_BF16DEV: return band_ib_st<LBM_BF16DEV>(c, ftot);
-    case LBM_F64: return band_ib_st<LBM_F64>(c, ftot);
+    case LBM_F32: return band_ib_st<LBM_F32>(c, state, ftot);
+    case LBM_F16DEV: return band_ib_st<LBM_F16DEV>(c, state, ftot);
+    case LBM_BF16DEV: return band_ib_st<LBM_BF16DEV>(c, state, ftot);
+    case LBM_F64: return band_ib_st<LBM_F64>(c, state, ftot);
     }
     return hipErrorInvalidValue;
 }

@@ -71,6 +71,15 @@ _SIG = {
     "lbm_state_bytes": [_vp, C.POINTER(_sz)],
     "lbm_checkpoint": [_vp, _vp],
     "lbm_restore": [_vp, _vp],
+    "lbm_set_gains": [_vp, _vp],
+    "lbm_record_tape": [_vp, _i32, _vp],
+    "lbm_adjoint_ws_size": [_vp, C.POINTER(_sz)],
+    "lbm_adjoint_init": [_vp, _vp, _sz],
+    "lbm_adjoint_seed_macros": [_vp, _vp, _vp, _vp],
+    "lbm_adjoint_seed_force": [_vp, C.POINTER(C.c_double), _vp, _vp],
+    "lbm_adjoint_step": [_vp, _i32, _vp, _vp, _vp],
+    "lbm_adjoint_get": [_vp, _vp],
+    "lbm_adjoint_set": [_vp, _vp],
 }
 for _name, _args in _SIG.items():
     _fn = getattr(_L, _name)
@@ -267,6 +276,57 @@ class Solver:
         if src.numel() * src.element_size() < self.state_bytes():
             raise LbmError(1, "snapshot too small")
         _check(_L.lbm_restore(self._h, _ptr(src)), self._h)
+
+
+    # ------------------------------------------------------------------
+    # adjoint
+    def set_gains(self, gain):
+        self._gain = torch.as_tensor(gain, device=self.device).to(torch.float32).contiguous()
+        _check(_L.lbm_set_gains(self._h, _ptr(self._gain)), self._h)
+
+    def record_tape(self, n: int, tape: torch.Tensor | None = None) -> torch.Tensor:
+        """Advance n steps, storing the state before each one (n x state_bytes)."""
+        sb = self.state_bytes()
+        if tape is None:
+            tape = torch.empty((max(n, 1), sb), dtype=torch.uint8, device=self.device)
+        if tape.numel() < n * sb:
+            raise LbmError(1, "tape too small")
+        _check(_L.lbm_record_tape(self._h, int(n), _ptr(tape)), self._h)
+        return tape
+
+    def adjoint_init(self):
+        n = C.c_size_t()
+        _check(_L.lbm_adjoint_ws_size(self._h, C.byref(n)), self._h)
+        self._aws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        _check(_L.lbm_adjoint_init(self._h, _ptr(self._aws), self._aws.numel()), self._h)
+
+    def new_grad_inlet(self) -> torch.Tensor:
+        nz, ny, _ = self.shape
+        return torch.zeros((3, nz, ny), dtype=torch.float64, device=self.device)
+
+    def new_grad_gain(self) -> torch.Tensor:
+        return torch.zeros(max(self.n_markers, 1), dtype=torch.float64, device=self.device)
+
+    def adjoint_seed_macros(self, g_rho=None, g_u=None, g_inlet=None):
+        gr = None if g_rho is None else self._real(g_rho, self.shape)
+        gu = None if g_u is None else self._real(g_u, (3,) + self.shape)
+        _check(_L.lbm_adjoint_seed_macros(self._h, _ptr(gr), _ptr(gu), _ptr(g_inlet)), self._h)
+
+    def adjoint_seed_force(self, g_force, g_inlet=None, g_gain=None):
+        gf = (C.c_double * 3)(*[float(v) for v in g_force])
+        _check(_L.lbm_adjoint_seed_force(self._h, gf, _ptr(g_inlet), _ptr(g_gain)), self._h)
+
+    def adjoint_step(self, n: int, tape: torch.Tensor, g_inlet=None, g_gain=None):
+        _check(_L.lbm_adjoint_step(self._h, int(n), _ptr(tape), _ptr(g_inlet), _ptr(g_gain)), self._h)
+
+    def adjoint_get(self) -> torch.Tensor:
+        lam = torch.empty((27,) + self.shape, dtype=self.real, device=self.device)
+        _check(_L.lbm_adjoint_get(self._h, _ptr(lam)), self._h)
+        return lam
+
+    def adjoint_set(self, lam):
+        self._lam = self._real(lam, (27,) + self.shape)
+        _check(_L.lbm_adjoint_set(self._h, _ptr(self._lam)), self._h)
 
 
 def version() -> str:

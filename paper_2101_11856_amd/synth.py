@@ -210,9 +210,9 @@ def inlet_coefficients(seed: int = 2105, n: int = 16, amp: float = 0.01) -> np.n
     return np.random.default_rng(seed).uniform(-amp, amp, n)
 
 
-def inlet_profile(ny: int, nz: int, coeffs, base: float = 0.04) -> np.ndarray:
+def inlet_profile(ny: int, nz: int, coeffs, base: float = 0.04, length: float = 64.0) -> np.ndarray:
     """u_x(y, z) = base + sum_pq a_pq phi_pq(y, z); u_y = u_z = 0; [3, nz, ny]."""
-    B = inlet_mode_basis(ny, nz)
+    B = inlet_mode_basis(ny, nz, length=length)
     prof = np.zeros((3, nz, ny))
     prof[0] = base + np.tensordot(np.asarray(coeffs, dtype=np.float64), B, axes=1)
     return prof
