@@ -118,6 +118,62 @@ def sphere_workload(steps, warmup):
     return out
 
 
+def city_workload(steps, warmup, storage="f32"):
+    """City blocks 1200x250x840 (252M cells): inlet wind, no-slip ground,
+    free-slip top, periodic z, 400 boxes with 3.86M samples, passive scalar."""
+    import torch
+
+    from paper_2101_11856_amd import lbm, synth
+    nx, ny, nz = 1200, 250, 840
+    s = lbm.Solver(nx, ny, nz, 1e-5, faces=(lbm.INLET, lbm.OUTFLOW, lbm.NOSLIP, lbm.FREESLIP, 0, 0),
+                   u_in=(0.05, 0.0, 0.0), storage=storage, scalar=True, scalar_inlet_height=50)
+    rho = torch.ones((nz, ny, nx), dtype=torch.float32, device="cuda")
+    u = torch.zeros((3, nz, ny, nx), dtype=torch.float32, device="cuda")
+    u[0] = 0.05
+    s.init_equilibrium(rho, u)
+    del rho, u
+    s.set_scalar(torch.zeros((nz, ny, nx), dtype=torch.float32, device="cuda"))
+    xyz, ub, area, gain = synth.city_markers(synth.city_boxes())
+    s.set_solids(xyz, ub, area, gain)
+    t = timed_steps(s, steps, warmup)
+    cells = nx * ny * nz
+    out = {"workload": f"city blocks 1200x250x840, {xyz.shape[1]} samples, passive scalar, {storage.upper()}",
+           "value": round(cells * steps / t / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(1e3 * t / steps, 3),
+           "samples": int(xyz.shape[1]), "cells": cells,
+           "population_bytes": 2 * 27 * cells * (4 if storage == "f32" else 2)}
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_workload(steps=2000, every=100):
+    """Adjoint channel 128x64x64, cylinder samples: forward with checkpoints,
+    then the reverse sweep (segment recompute + adjoint steps)."""
+    import torch
+
+    from paper_2101_11856_amd import synth
+    from paper_2101_11856_amd.adjoint import AdjointRun, ChannelProblem
+    p = ChannelProblem(steps=steps, checkpoint_every=every)
+    a = torch.tensor(synth.inlet_coefficients(seed=2105), dtype=torch.float64, device="cuda", requires_grad=True)
+    g = torch.ones(p.n, dtype=torch.float64, device="cuda", requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    drag, probe = AdjointRun.apply(p, a, g)
+    J = p.objective(drag, probe)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    cells = p.nx * p.ny * p.nz
+    return {"workload": f"adjoint channel 128x64x64, {p.n} cylinder samples, {steps} steps, checkpoint every {every}, "
+                        "FP32", "forward_ms_per_step": round(1e3 * (t1 - t0) / steps, 4),
+            "backward_ms_per_step": round(1e3 * (t2 - t1) / steps, 4),
+            "backward_MLUPS": round(cells * steps / (t2 - t1) / 1e6, 1),
+            "note": "backward = segment recompute with tape + adjoint step; wall clock incl. host launch overhead",
+            "J": float(J), "grad_norm_coeffs": float(a.grad.norm())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +185,8 @@ def main():
     ap.add_argument("--storage", default="f32", help="population storage of --profile-pass")
     ap.add_argument("--profile-pass", action="store_true",
                     help="profiler pass: the workload only, then 3 state copies of known size (calibration)")
+    ap.add_argument("--workload", default="turbulence", choices=["turbulence", "sphere", "city"],
+                    help="workload of --profile-pass")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -141,6 +199,13 @@ def main():
     import torch
 
     from paper_2101_11856_amd import synth
+
+    if args.profile_pass and args.workload == "sphere":
+        print(json.dumps(sphere_workload(args.steps, args.warmup)), flush=True)
+        return
+    if args.profile_pass and args.workload == "city":
+        print(json.dumps(city_workload(args.steps, args.warmup, args.storage)), flush=True)
+        return
 
     n = args.n
     log(f"generating turbulence field {n}^3")
@@ -216,6 +281,11 @@ def main():
             torch.cuda.empty_cache()
         log("sphere run")
         result["ib_sphere"] = sphere_workload(min(args.steps, 100), min(args.warmup, 10))
+        for storage in ("f32", "f16"):
+            log(f"city run {storage}")
+            result[f"city_{storage}"] = city_workload(min(args.steps, 50), min(args.warmup, 5), storage)
+        log("adjoint run")
+        result["adjoint_channel"] = adjoint_workload()
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -487,6 +487,7 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
     L->band_cell = take(nbmax * 4);
     L->band_ru = take(nbmax * 4 * c->rsize);
     L->band_force = take(nbmax * 4 * c->rsize);
+    L->ib_part = take(((un + 255) / 256) * 4 * 8);
     L->misc = take(256);
     L->total = o;
     return hipSuccess;
@@ -532,6 +533,7 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
     c->band_cell = reinterpret_cast<int32_t *>(m + L.band_cell);
     c->band_ru = m + L.band_ru;
     c->band_force = m + L.band_force;
+    c->ib_part = reinterpret_cast<double *>(m + L.ib_part);
     hipLaunchKernelGGL(k_mk_gather, grid_for(n), dim3(256), 0, st, n, perm, xyz, ub, area, gain, c->m_pos, c->m_ub,
                        c->m_area, c->m_gain);
     if ((e = launch_zero(c, c->tile_mask, (size_t)c->g.W * 8)) != hipSuccess) return e;

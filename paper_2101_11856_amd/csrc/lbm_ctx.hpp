@@ -46,6 +46,7 @@ struct lbm_ctx {
     int32_t *band_cell = nullptr;  // [nband]
     void *band_ru = nullptr;       // [nband] real4 (rho, u)
     void *band_force = nullptr;    // [nband] real4 (g, 0)
+    double *ib_part = nullptr;     // [ceil(nm/256)][4] per-block force partials
     // adjoint workspace (caller-owned)
     char *aws = nullptr;
     size_t aws_bytes = 0;
@@ -61,7 +62,7 @@ namespace lbm {
 // Marker workspace carve-up, shared by the size query and lbm_set_solids.
 struct SolidsLayout {
     size_t pos, ub, area, gain, slot, cell, perm, keys_in, keys_out, idx_in, sort_tmp, sort_tmp_bytes;
-    size_t tile_mask, tile_start, tile_count, scan_tmp, scan_tmp_bytes, band_cell, band_ru, band_force, misc;
+    size_t tile_mask, tile_start, tile_count, scan_tmp, scan_tmp_bytes, band_cell, band_ru, band_force, ib_part, misc;
     size_t total;
 };
 hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L);

@@ -112,21 +112,15 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
 
 // ---------------------------------------------------------------------------
 // band pre-pass: streamed rho and u0 = j/rho of every band node; clears the
-// band force and the force total
+// band force
 // ---------------------------------------------------------------------------
 template <int ST>
 __global__ void __launch_bounds__(256)
     k_band(const StepParams<ST> P, const int32_t *__restrict__ band_cell, int64_t nband,
-           typename StepParams<ST>::R4 *__restrict__ band_ru, typename StepParams<ST>::R4 *__restrict__ band_force,
-           double *__restrict__ ftot)
+           typename StepParams<ST>::R4 *__restrict__ band_ru, typename StepParams<ST>::R4 *__restrict__ band_force)
 {
     using R = typename Store<ST>::R;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b == 0) {
-        ftot[0] = 0.0;
-        ftot[1] = 0.0;
-        ftot[2] = 0.0;
-    }
     if (b >= nband) return;
     const Geom &g = P.g;
     const int64_t cell = band_cell[b];
@@ -160,7 +154,7 @@ template <typename R> struct IbParams {
     const int32_t *__restrict__ slot;  // [8][n]
     const R4 *__restrict__ band_ru;
     R4 *__restrict__ band_force;
-    double *__restrict__ ftot;
+    double *__restrict__ part;  // [gridDim.x][4] per-block force totals
 };
 
 template <typename R>
@@ -201,16 +195,21 @@ __global__ void __launch_bounds__(256) k_ib(const IbParams<R> P)
 #pragma unroll
     for (int a = 0; a < 3; ++a) aG[a] = valid ? ar * gam * rs * ((R)P.ub[a * n + sc] - us[a]) : (R)0;
 
-    // FP64 total force: wave reduction, one atomic per wave and component
+    // FP64 total force: wave reduction, then one partial per block (no
+    // same-address atomics; the partials are summed in order afterwards)
+    __shared__ double wsum[4][3];
     double tot[3] = {(double)aG[0], (double)aG[1], (double)aG[2]};
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
         for (int a = 0; a < 3; ++a) tot[a] += __shfl_down(tot[a], off, 64);
-    if (lane == 0) {
+    if (lane == 0)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) unsafeAtomicAdd(P.ftot + a, tot[a]);
-    }
+        for (int a = 0; a < 3; ++a) wsum[threadIdx.x >> 6][a] = tot[a];
+    __syncthreads();
+    if (threadIdx.x < 3)
+        P.part[4 * blockIdx.x + threadIdx.x] =
+            wsum[0][threadIdx.x] + wsum[1][threadIdx.x] + wsum[2][threadIdx.x] + wsum[3][threadIdx.x];
 
     // Eq. (8) by scattering: samples of one base cell are contiguous in the
     // sorted order and share all 8 targets; a segmented suffix sum over the
@@ -244,6 +243,26 @@ __global__ void __launch_bounds__(256) k_ib(const IbParams<R> P)
             unsafeAtomicAdd(dst + 2, v[d][2]);
         }
     }
+}
+
+// ordered sum of the per-block force partials (deterministic FP64 total)
+__global__ void __launch_bounds__(256) k_ib_total(const double *__restrict__ part, int nblk, double *__restrict__ ftot)
+{
+    __shared__ double sh[3][256];
+    double acc[3] = {0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[a] += part[4 * b + a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sh[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) ftot[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -305,7 +324,7 @@ template <int ST> static hipError_t band_ib_st(lbm_ctx *c, const void *state, do
     P.fin = static_cast<const typename Store<ST>::T *>(state);
     const unsigned nb = (unsigned)((c->nband + 255) / 256);
     hipLaunchKernelGGL((k_band<ST>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, P, c->band_cell, c->nband,
-                       static_cast<R4 *>(c->band_ru), static_cast<R4 *>(c->band_force), ftot);
+                       static_cast<R4 *>(c->band_ru), static_cast<R4 *>(c->band_force));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     IbParams<R> Q{};
@@ -317,8 +336,10 @@ template <int ST> static hipError_t band_ib_st(lbm_ctx *c, const void *state, do
     Q.slot = c->m_slot;
     Q.band_ru = static_cast<const R4 *>(c->band_ru);
     Q.band_force = static_cast<R4 *>(c->band_force);
-    Q.ftot = ftot;
-    hipLaunchKernelGGL((k_ib<R>), dim3((unsigned)((c->nm + 255) / 256)), dim3(256), 0, c->stream, Q);
+    Q.part = c->ib_part;
+    const int nblk = (int)((c->nm + 255) / 256);
+    hipLaunchKernelGGL((k_ib<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
+    hipLaunchKernelGGL(k_ib_total, dim3(1), dim3(256), 0, c->stream, c->ib_part, nblk, ftot);
     return hipGetLastError();
 }
 
