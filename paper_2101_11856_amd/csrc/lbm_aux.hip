@@ -317,6 +317,39 @@ __global__ void k_mk_slots(MarkerGeom mg, int64_t n, const float *__restrict__ p
     }
 }
 
+// runs of sorted samples that share a base cell (slot of stencil offset 0)
+__global__ void k_run_heads(int64_t n, const int32_t *__restrict__ slot0, int32_t *__restrict__ head)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) head[k] = (k == 0 || slot0[k] != slot0[k - 1]) ? 1 : 0;
+}
+
+__global__ void k_run_start(int64_t n, const int32_t *__restrict__ head, const int32_t *__restrict__ run_id,
+                            int32_t *__restrict__ run_start)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (head[k]) run_start[run_id[k]] = (int32_t)k;
+    if (k == n - 1) run_start[run_id[k] + head[k]] = (int32_t)n;
+}
+
+__global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+// band node t = base(run r) + d is fed by run r through offset d (one base
+// per target and offset, so no two runs write the same entry)
+__global__ void k_band_src(int64_t nruns, int64_t n, int64_t nband, const int32_t *__restrict__ run_start,
+                           const int32_t *__restrict__ slot, int32_t *__restrict__ band_src)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nruns) return;
+    const int64_t k0 = run_start[r];
+    for (int d = 0; d < 8; ++d) band_src[(int64_t)d * nband + slot[(int64_t)d * n + k0]] = (int32_t)r;
+}
+
 __global__ void k_flags_band(MarkerGeom mg, int64_t N, const unsigned long long *__restrict__ mask,
                              uint8_t *__restrict__ flags)
 {
@@ -480,7 +513,8 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
     L->tile_start = take(W * 4);
     L->tile_count = take(W * 4);
     size_t scan_bytes = 0;
-    e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int32_t *)nullptr, (int32_t *)nullptr, (int)W);
+    e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int32_t *)nullptr, (int32_t *)nullptr,
+                                         (int)std::max<size_t>(W, un));
     if (e != hipSuccess) return e;
     L->scan_tmp_bytes = scan_bytes;
     L->scan_tmp = take(scan_bytes);
@@ -488,6 +522,11 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
     L->band_ru = take(nbmax * 4 * c->rsize);
     L->band_force = take(nbmax * 4 * c->rsize);
     L->ib_part = take(((un + 255) / 256) * 4 * 8);
+    L->run_head = take(un * 4);
+    L->run_id = take(un * 4);
+    L->run_start = take((un + 1) * 4);
+    L->run_sum = take(8 * un * 4 * c->rsize);
+    L->band_src = take(8 * nbmax * 4);
     L->misc = take(256);
     L->total = o;
     return hipSuccess;
@@ -557,6 +596,25 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
                        reinterpret_cast<const unsigned long long *>(c->tile_mask), c->tile_start, c->band_cell);
     hipLaunchKernelGGL(k_mk_slots, grid_for(n), dim3(256), 0, st, mg, n, c->m_pos,
                        reinterpret_cast<const unsigned long long *>(c->tile_mask), c->tile_start, c->m_slot);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // runs of samples with one base cell, and the run feeding each band node
+    int32_t *head = reinterpret_cast<int32_t *>(m + L.run_head);
+    int32_t *rid = reinterpret_cast<int32_t *>(m + L.run_id);
+    c->run_start = reinterpret_cast<int32_t *>(m + L.run_start);
+    c->run_sum = m + L.run_sum;
+    c->band_src = reinterpret_cast<int32_t *>(m + L.band_src);
+    hipLaunchKernelGGL(k_run_heads, grid_for(n), dim3(256), 0, st, n, c->m_slot, head);
+    scan_bytes = L.scan_tmp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(m + L.scan_tmp, scan_bytes, head, rid, (int)n, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_run_start, grid_for(n), dim3(256), 0, st, n, head, rid, c->run_start);
+    if ((e = hipMemcpyAsync(&tail[0], rid + (n - 1), 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&tail[1], head + (n - 1), 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    c->nruns = (int64_t)tail[0] + tail[1];
+    hipLaunchKernelGGL(k_fill_i32, grid_for(8 * c->nband), dim3(256), 0, st, c->band_src, 8 * c->nband, -1);
+    hipLaunchKernelGGL(k_band_src, grid_for(c->nruns), dim3(256), 0, st, c->nruns, n, c->nband, c->run_start,
+                       c->m_slot, c->band_src);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return hipStreamSynchronize(st);
 }

@@ -46,7 +46,11 @@ struct lbm_ctx {
     int32_t *band_cell = nullptr;  // [nband]
     void *band_ru = nullptr;       // [nband] real4 (rho, u)
     void *band_force = nullptr;    // [nband] real4 (g, 0)
-    double *ib_part = nullptr;     // [ceil(nm/256)][4] per-block force partials
+    double *ib_part = nullptr;     // [ceil(nruns/256)][4] per-block force partials
+    int64_t nruns = 0;             // runs of samples sharing a base cell (sorted order)
+    int32_t *run_start = nullptr;  // [nruns + 1] first sorted sample of each run
+    void *run_sum = nullptr;       // [8][nruns] real4: a K_d g summed over the run, per stencil offset d
+    int32_t *band_src = nullptr;   // [8][nband] run feeding band node j through offset d, or -1
     // adjoint workspace (caller-owned)
     char *aws = nullptr;
     size_t aws_bytes = 0;
@@ -63,6 +67,7 @@ namespace lbm {
 struct SolidsLayout {
     size_t pos, ub, area, gain, slot, cell, perm, keys_in, keys_out, idx_in, sort_tmp, sort_tmp_bytes;
     size_t tile_mask, tile_start, tile_count, scan_tmp, scan_tmp_bytes, band_cell, band_ru, band_force, ib_part, misc;
+    size_t run_head, run_id, run_start, run_sum, band_src;
     size_t total;
 };
 hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L);

@@ -111,13 +111,12 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
 }
 
 // ---------------------------------------------------------------------------
-// band pre-pass: streamed rho and u0 = j/rho of every band node; clears the
-// band force
+// band pre-pass: streamed rho and u0 = j/rho of every band node
 // ---------------------------------------------------------------------------
 template <int ST>
 __global__ void __launch_bounds__(256)
     k_band(const StepParams<ST> P, const int32_t *__restrict__ band_cell, int64_t nband,
-           typename StepParams<ST>::R4 *__restrict__ band_ru, typename StepParams<ST>::R4 *__restrict__ band_force)
+           typename StepParams<ST>::R4 *__restrict__ band_ru)
 {
     using R = typename Store<ST>::R;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -137,68 +136,90 @@ __global__ void __launch_bounds__(256)
     v.z = m.jy * inv;
     v.w = m.jz * inv;
     band_ru[b] = v;
-    v.x = v.y = v.z = v.w = (R)0;
-    band_force[b] = v;
 }
 
 // ---------------------------------------------------------------------------
-// immersed boundary: one lane per sorted sample
+// immersed boundary (Eqs. 6-8), spreading in two deterministic phases
+//   k_ib_run: one lane per run of sorted samples sharing a base cell (the
+//     samples of one cell are contiguous, Sec. 4.2.2 order).  The run's 8
+//     stencil nodes and their (rho, u0) are loaded once; each sample adds
+//     a_s K_d g_s to a register accumulator per offset d; the run stores its
+//     8 sums (no atomics).
+//   k_spread: one lane per band node gathers the (at most 8) run sums that
+//     target it, in a fixed order.
 // ---------------------------------------------------------------------------
 template <typename R> struct IbParams {
     using R4 = typename R4T<R>::type;
-    int64_t n;
-    const float *__restrict__ pos;   // [3][n] sorted
-    const float *__restrict__ ub;    // [3][n]
-    const float *__restrict__ area;  // [n]
-    const float *__restrict__ gain;  // [n]
-    const int32_t *__restrict__ slot;  // [8][n]
+    int64_t n, nruns, nband;
+    const int32_t *__restrict__ run_start;  // [nruns + 1]
+    const float *__restrict__ pos;          // [3][n] sorted
+    const float *__restrict__ ub;           // [3][n]
+    const float *__restrict__ area;         // [n]
+    const float *__restrict__ gain;         // [n]
+    const int32_t *__restrict__ slot;       // [8][n]
     const R4 *__restrict__ band_ru;
-    R4 *__restrict__ band_force;
-    double *__restrict__ part;  // [gridDim.x][4] per-block force totals
+    R4 *__restrict__ run_sum;               // [8][nruns]
+    double *__restrict__ part;              // [gridDim.x][4] per-block force totals
 };
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_ib(const IbParams<R> P)
+__global__ void __launch_bounds__(256) k_ib_run(const IbParams<R> P)
 {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    using R4 = typename R4T<R>::type;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const bool valid = s < P.n;
-    const int64_t sc = valid ? s : P.n - 1;
     const int64_t n = P.n;
-
-    // Eq. (6): trilinear weights of the 2x2x2 stencil, delta = dx + 2 dy + 4 dz
-    R t[3];
+    double tot[3] = {0.0, 0.0, 0.0};
+    if (r < P.nruns) {
+        const int64_t k0 = P.run_start[r], k1 = P.run_start[r + 1];
+        R4 node[8];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float p = P.pos[a * n + sc];
-        t[a] = (R)(p - floorf(p));
+        for (int d = 0; d < 8; ++d) node[d] = P.band_ru[P.slot[(int64_t)d * n + k0]];
+        R acc[8][3];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) acc[d][0] = acc[d][1] = acc[d][2] = (R)0;
+        for (int64_t k = k0; k < k1; ++k) {
+            R t[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float p = P.pos[a * n + k];
+                t[a] = (R)(p - floorf(p));
+            }
+            R K[8], rs = 0, us[3] = {0, 0, 0};
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                K[d] = ((d & 1) ? t[0] : (R)1 - t[0]) * ((d & 2) ? t[1] : (R)1 - t[1]) * ((d & 4) ? t[2] : (R)1 - t[2]);
+                rs += K[d] * node[d].x;
+                us[0] += K[d] * node[d].y;
+                us[1] += K[d] * node[d].z;
+                us[2] += K[d] * node[d].w;
+            }
+            // Eq. (7) with the sample's gain; Eq. (8) carries the area weight
+            const R ag = (R)P.area[k] * (R)P.gain[k] * rs;
+            R aG[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                aG[a] = ag * ((R)P.ub[a * n + k] - us[a]);
+                tot[a] += (double)aG[a];
+            }
+#pragma unroll
+            for (int d = 0; d < 8; ++d)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) acc[d][a] += K[d] * aG[a];
+        }
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            R4 v;
+            v.x = acc[d][0];
+            v.y = acc[d][1];
+            v.z = acc[d][2];
+            v.w = (R)0;
+            P.run_sum[(int64_t)d * P.nruns + r] = v;
+        }
     }
-    int32_t sl[8];
-    R K[8];
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        sl[d] = P.slot[(int64_t)d * n + sc];
-        K[d] = ((d & 1) ? t[0] : (R)1 - t[0]) * ((d & 2) ? t[1] : (R)1 - t[1]) * ((d & 4) ? t[2] : (R)1 - t[2]);
-    }
-    R rs = 0, us[3] = {0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        const auto v = P.band_ru[sl[d]];
-        rs += K[d] * v.x;
-        us[0] += K[d] * v.y;
-        us[1] += K[d] * v.z;
-        us[2] += K[d] * v.w;
-    }
-    // Eq. (7) with the sample's gain; Eq. (8) carries the area weight
-    const R gam = (R)P.gain[sc], ar = (R)P.area[sc];
-    R aG[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) aG[a] = valid ? ar * gam * rs * ((R)P.ub[a * n + sc] - us[a]) : (R)0;
-
     // FP64 total force: wave reduction, then one partial per block (no
     // same-address atomics; the partials are summed in order afterwards)
     __shared__ double wsum[4][3];
-    double tot[3] = {(double)aG[0], (double)aG[1], (double)aG[2]};
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
@@ -210,39 +231,28 @@ __global__ void __launch_bounds__(256) k_ib(const IbParams<R> P)
     if (threadIdx.x < 3)
         P.part[4 * blockIdx.x + threadIdx.x] =
             wsum[0][threadIdx.x] + wsum[1][threadIdx.x] + wsum[2][threadIdx.x] + wsum[3][threadIdx.x];
+}
 
-    // Eq. (8) by scattering: samples of one base cell are contiguous in the
-    // sorted order and share all 8 targets; a segmented suffix sum over the
-    // run leaves the run total in its first lane, which alone adds it.
-    const int key = valid ? sl[0] : -1;  // slot of the base cell identifies the run
-    R v[8][3];
+template <typename R>
+__global__ void __launch_bounds__(256) k_spread(int64_t nband, int64_t nruns, const int32_t *__restrict__ band_src,
+                                                const typename R4T<R>::type *__restrict__ run_sum,
+                                                typename R4T<R>::type *__restrict__ band_force)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nband) return;
+    typename R4T<R>::type g;
+    g.x = g.y = g.z = g.w = (R)0;
 #pragma unroll
-    for (int d = 0; d < 8; ++d)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) v[d][a] = K[d] * aG[a];
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int k2 = __shfl_down(key, off, 64);
-        const bool same = (lane + off < 64) && (k2 == key);
-#pragma unroll
-        for (int d = 0; d < 8; ++d)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const R o = __shfl_down(v[d][a], off, 64);
-                if (same) v[d][a] += o;
-            }
-    }
-    const int kprev = __shfl_up(key, 1, 64);
-    const bool head = valid && (lane == 0 || kprev != key);
-    if (head) {
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            R *dst = reinterpret_cast<R *>(P.band_force + sl[d]);
-            unsafeAtomicAdd(dst + 0, v[d][0]);
-            unsafeAtomicAdd(dst + 1, v[d][1]);
-            unsafeAtomicAdd(dst + 2, v[d][2]);
+    for (int d = 0; d < 8; ++d) {
+        const int32_t src = band_src[(int64_t)d * nband + j];
+        if (src >= 0) {
+            const auto v = run_sum[(int64_t)d * nruns + src];
+            g.x += v.x;
+            g.y += v.y;
+            g.z += v.z;
         }
     }
+    band_force[j] = g;
 }
 
 // ordered sum of the per-block force partials (deterministic FP64 total)
@@ -324,22 +334,25 @@ template <int ST> static hipError_t band_ib_st(lbm_ctx *c, const void *state, do
     P.fin = static_cast<const typename Store<ST>::T *>(state);
     const unsigned nb = (unsigned)((c->nband + 255) / 256);
     hipLaunchKernelGGL((k_band<ST>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, P, c->band_cell, c->nband,
-                       static_cast<R4 *>(c->band_ru), static_cast<R4 *>(c->band_force));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+                       static_cast<R4 *>(c->band_ru));
     IbParams<R> Q{};
     Q.n = c->nm;
+    Q.nruns = c->nruns;
+    Q.nband = c->nband;
+    Q.run_start = c->run_start;
     Q.pos = c->m_pos;
     Q.ub = c->m_ub;
     Q.area = c->m_area;
     Q.gain = c->m_gain;
     Q.slot = c->m_slot;
     Q.band_ru = static_cast<const R4 *>(c->band_ru);
-    Q.band_force = static_cast<R4 *>(c->band_force);
+    Q.run_sum = static_cast<R4 *>(c->run_sum);
     Q.part = c->ib_part;
-    const int nblk = (int)((c->nm + 255) / 256);
-    hipLaunchKernelGGL((k_ib<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
+    const int nblk = (int)((c->nruns + 255) / 256);
+    hipLaunchKernelGGL((k_ib_run<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
     hipLaunchKernelGGL(k_ib_total, dim3(1), dim3(256), 0, c->stream, c->ib_part, nblk, ftot);
+    hipLaunchKernelGGL((k_spread<R>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, c->nband, c->nruns,
+                       c->band_src, static_cast<const R4 *>(c->run_sum), static_cast<R4 *>(c->band_force));
     return hipGetLastError();
 }
 
