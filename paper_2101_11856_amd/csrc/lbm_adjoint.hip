@@ -62,8 +62,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(const AdjParams<ST> P)
     const bool active = x < g.nx;
     const int xc = active ? x : g.nx - 1;
     R f[3][3][3];
-    if (wave_touches_face(xs, y, z, g)) pull_general<ST>(f, P.fin, xc, y, z, g, P.inlet);
-    else pull_interior<ST>(f, P.fin, xc, y, z, g);
+    pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
     R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
     int slot = -1;
     if (BAND) {
@@ -224,7 +223,7 @@ __global__ void __launch_bounds__(256) k_adj_seed_macros(Geom g, const typename 
     const int64_t r = k / g.nx;
     const int y = (int)(r % g.ny), z = (int)(r / g.ny);
     R f[3][3][3];
-    pull_general<ST>(f, fin, x, y, z, g, inl);
+    pull_node<ST>(f, fin, x, y, z, g, inl);
     const Macro<R> m = moments01(f);
     const R rho = (R)1 + m.drho, inv = (R)1 / rho;
     const R u[3] = {m.jx * inv, m.jy * inv, m.jz * inv};

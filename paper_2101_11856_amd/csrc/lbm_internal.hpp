@@ -76,14 +76,8 @@ template <> struct Store<LBM_BF16DEV> {
     using T = uint16_t;
     using R = float;
     __device__ static R dec(T v) { return __uint_as_float(((uint32_t)v) << 16); }
-    __device__ static T enc(R v)
-    {
-        // round to nearest even on the upper 16 bits; NaN stays NaN
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (T)((u >> 16) | 0x40);
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return (T)(u >> 16);
-    }
+    // round to nearest even (gfx950 converts natively: v_cvt_pk_bf16_f32)
+    __device__ static T enc(R v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 };
 
 // ---------------------------------------------------------------------------
@@ -105,6 +99,17 @@ template <> struct Store<LBM_BF16DEV> {
 // one work item, a workgroup LBM_WAVES consecutive ones.
 constexpr int SEG = 64;
 constexpr int WAVES_PER_BLOCK = LBM_WAVES;
+
+// base + 32-bit byte offset: with a wave-uniform base this selects the
+// scalar-base / 32-bit vector-offset memory form (no 64-bit address math)
+template <typename T> __device__ __forceinline__ const T *at_bytes(const T *base, uint32_t byte_off)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T> __device__ __forceinline__ T *at_bytes(T *base, uint32_t byte_off)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+}
 
 // streaming read of a population (used once per step, except the one-element
 // overlap of neighbouring segments, which the L2 still catches)
@@ -213,13 +218,6 @@ __device__ __forceinline__ PullSrc resolve(int i, int x, int y, int z, const Geo
     return {i, px, py, pz, 0};  // not reached for valid geometry
 }
 
-__device__ __forceinline__ bool wave_touches_face(int xs, int y, int z, const Geom &g)
-{
-    return (xs == 0 && g.face[0] != LBM_PERIODIC) || (xs == g.ntx - 1 && g.face[1] != LBM_PERIODIC) ||
-           (y == 0 && g.face[2] != LBM_PERIODIC) || (y == g.ny - 1 && g.face[3] != LBM_PERIODIC) ||
-           (z == 0 && g.face[4] != LBM_PERIODIC) || (z == g.nz - 1 && g.face[5] != LBM_PERIODIC);
-}
-
 // Inlet velocity at row (y, z): profile [3][nz][ny] or uniform.
 template <typename R> struct Inlet {
     const R *prof;
@@ -272,15 +270,94 @@ __device__ __forceinline__ void pull_interior(R (&f)[3][3][3], const typename St
     const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-    const int xs[3] = {xp, x, xm};  // source x for c_x = -1, 0, +1
+    // per-lane 32-bit offsets; plane and row bases are wave-uniform, so each
+    // load is a scalar base plus a 32-bit vector offset (no 64-bit VALU math)
+    using T = typename Store<ST>::T;
+    const uint32_t xs[3] = {(uint32_t)(xp * sizeof(T)), (uint32_t)(x * sizeof(T)),
+                            (uint32_t)(xm * sizeof(T))};  // byte offset of source x for c_x = -1, 0, +1
     const int ys[3] = {yp, y, ym};
     const int zs[3] = {zp, z, zm};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int row = (zs[CZ[i] + 1] * g.ny + ys[CY[i] + 1]) * g.nxp;
-        const typename Store<ST>::T *pl = in + (int64_t)i * g.plane + row;
-        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(ld_stream(pl + xs[CX[i] + 1]));
+        const int64_t row = ((int64_t)zs[CZ[i] + 1] * g.ny + ys[CY[i] + 1]) * g.nxp;
+        const T *pl = in + ((int64_t)i * g.plane + row);
+        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(ld_stream(at_bytes(pl, xs[CX[i] + 1])));
     }
+}
+
+// Pull for a wave that touches a non-periodic x face but no y or z face (an
+// x-segment at either end of a row).  Directions with c_x = 0 read as in the
+// interior.  The others select per lane between the plain source and the face
+// rule's source (lanes at x = 0 for c_x = +1, x = nx-1 for c_x = -1), so each
+// population is still one load: no-slip / inlet read the opposite population
+// at the node itself (the inlet adds 2 w_i (c_i.u_in)/cs^2), free slip reads
+// the x-reflected population across y, z, outflow reads the last layer.
+template <int ST, typename R>
+__device__ __forceinline__ void pull_xface(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int x, int y,
+                                           int z, const Geom &g, const Inlet<R> &inl)
+{
+    using T = typename Store<ST>::T;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    const int ys[3] = {yp, y, ym};
+    const int zs[3] = {zp, z, zm};
+    const int64_t row_own = ((int64_t)z * g.ny + y) * g.nxp;
+    const int F0 = g.face[0], F1 = g.face[1];
+    const bool lo = x == 0, hi = x == g.nx - 1;
+    const R uin[3] = {inl.at(0, y, z, g.ny, g.nz), inl.at(1, y, z, g.ny, g.nz), inl.at(2, y, z, g.ny, g.nz)};
+    const uint32_t xb = (uint32_t)(x * sizeof(T));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = CX[i];
+        const int64_t row_src = ((int64_t)zs[CZ[i] + 1] * g.ny + ys[CY[i] + 1]) * g.nxp;
+        const T *nb = in + ((int64_t)i * g.plane + row_src);
+        R v;
+        if (cx == 0) {
+            v = Store<ST>::dec(ld_stream(at_bytes(nb, xb)));
+        } else {
+            const bool cross = cx > 0 ? lo : hi;
+            const int Fc = cx > 0 ? F0 : F1;
+            const int rx = pop_index(-CX[i], CY[i], CZ[i]);
+            const T *ab = Fc == LBM_FREESLIP ? in + ((int64_t)rx * g.plane + row_src)
+                          : Fc == LBM_OUTFLOW ? nb
+                                              : in + ((int64_t)opp(i) * g.plane + row_own);
+            const uint32_t axb = Fc == LBM_OUTFLOW ? (uint32_t)((g.nx - 1) * sizeof(T)) : xb;
+            const uint32_t nxb = (uint32_t)((x - cx) * sizeof(T));
+            const T *p = cross ? at_bytes(ab, axb) : at_bytes(nb, nxb);
+            v = Store<ST>::dec(ld_stream(p));
+            if (cx > 0 && Fc == LBM_INLET && cross)
+                v += (R)(6.0 * weight(i)) * ((R)CX[i] * uin[0] + (R)CY[i] * uin[1] + (R)CZ[i] * uin[2]);
+        }
+        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = v;
+    }
+}
+
+// Wave-level choice of the pull (all lanes of a wave share y, z and the
+// segment): the face-aware general form only for rows on a y or z face.
+template <int ST, typename R>
+__device__ __forceinline__ void pull_wave(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int xs, int x,
+                                          int y, int z, const Geom &g, const Inlet<R> &inl)
+{
+    const bool yz = (y == 0 && g.face[2] != LBM_PERIODIC) || (y == g.ny - 1 && g.face[3] != LBM_PERIODIC) ||
+                    (z == 0 && g.face[4] != LBM_PERIODIC) || (z == g.nz - 1 && g.face[5] != LBM_PERIODIC);
+    const bool xf = (xs == 0 && g.face[0] != LBM_PERIODIC) || (xs == g.ntx - 1 && g.face[1] != LBM_PERIODIC);
+    if (yz) pull_general<ST>(f, in, x, y, z, g, inl);
+    else if (xf) pull_xface<ST>(f, in, x, y, z, g, inl);
+    else pull_interior<ST>(f, in, x, y, z, g);
+}
+
+// Per-node choice for kernels whose lanes hold unrelated nodes (band nodes,
+// dense macros): the plain periodic pull when no source crosses a
+// non-periodic face, the face-aware one otherwise.
+template <int ST, typename R>
+__device__ __forceinline__ void pull_node(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int x, int y,
+                                          int z, const Geom &g, const Inlet<R> &inl)
+{
+    const bool free = (x > 0 || g.face[0] == LBM_PERIODIC) && (x < g.nx - 1 || g.face[1] == LBM_PERIODIC) &&
+                      (y > 0 || g.face[2] == LBM_PERIODIC) && (y < g.ny - 1 || g.face[3] == LBM_PERIODIC) &&
+                      (z > 0 || g.face[4] == LBM_PERIODIC) && (z < g.nz - 1 || g.face[5] == LBM_PERIODIC);
+    if (free) pull_interior<ST>(f, in, x, y, z, g);
+    else pull_general<ST>(f, in, x, y, z, g, inl);
 }
 
 // ---------------------------------------------------------------------------

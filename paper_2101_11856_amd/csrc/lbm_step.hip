@@ -84,8 +84,7 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     const int xc = active ? x : g.nx - 1;
 
     R f[3][3][3];
-    if (wave_touches_face(xs, y, z, g)) pull_general<ST>(f, P.fin, xc, y, z, g, P.inlet);
-    else pull_interior<ST>(f, P.fin, xc, y, z, g);
+    pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
 
     R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
     if (BAND) {
@@ -101,11 +100,12 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     R rho, ux, uy, uz;
     collide(f, Fx, Fy, Fz, P.rt, rho, ux, uy, uz);
     if (active) {
-        const int64_t base = ((int64_t)z * g.ny + y) * g.nxp + x;
+        const int64_t row = ((int64_t)z * g.ny + y) * g.nxp;  // wave-uniform
+        const uint32_t xb = (uint32_t)(x * sizeof(typename Store<ST>::T));
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             __builtin_nontemporal_store(Store<ST>::enc(f[CZ[i] + 1][CY[i] + 1][CX[i] + 1]),
-                                        P.fout + (int64_t)i * g.plane + base);
+                                        at_bytes(P.fout + ((int64_t)i * g.plane + row), xb));
     }
     if (SCALAR) scalar_update<ST>(P, xc, y, z, (float)ux, (float)uy, (float)uz, active);
 }
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256)
     const int64_t r = cell / g.nx;
     const int y = (int)(r % g.ny), z = (int)(r / g.ny);
     R f[3][3][3];
-    pull_general<ST>(f, P.fin, x, y, z, g, P.inlet);
+    pull_node<ST>(f, P.fin, x, y, z, g, P.inlet);
     const Macro<R> m = moments01(f);
     const R rho = (R)1 + m.drho, inv = (R)1 / rho;
     typename StepParams<ST>::R4 v;
