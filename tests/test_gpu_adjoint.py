@@ -225,6 +225,36 @@ def test_adjoint_matches_oracle_finite_differences(small_fd, storage, gate):
 
 
 # ---------------------------------------------------------------------------
+# exact reference: torch.autograd through the independent FP64 model
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,gate", [("f64", 1e-9), ("f32", 1e-3)])
+def test_adjoint_matches_fp64_autograd_model(storage, gate):
+    """Every component of both gradients (16 inflow coefficients, one gain
+    per sample) against the exact gradient of the plain-PyTorch FP64 model,
+    whose objective equals the C oracle's."""
+    from paper_2101_11856_amd.adjoint import AdjointRun, ChannelProblem
+    from tests.test_oracle_autograd import CHANNEL, TINY, _gains, _markers, autograd_J
+    c = dict(TINY, steps=20)
+    coeffs = 0.5 * synth.inlet_coefficients(seed=2105)
+    gains = _gains(_markers(c)[0].shape[1])
+    J_ref, ga_ref, gg_ref = autograd_J(c, CHANNEL, coeffs, gains)
+    say(f"adjoint vs FP64 autograd model, tiny channel, storage={storage}")
+    prob = ChannelProblem(nx=c["nx"], ny=c["ny"], nz=c["nz"], nu=c["nu"], steps=c["steps"], checkpoint_every=6,
+                          storage=storage, probe_x=c["probe_x"], radius=c["radius"], center=c["center"],
+                          n_around=c["n_around"], mode_length=c["mode_length"])
+    a = torch.tensor(coeffs, dtype=torch.float64, device="cuda", requires_grad=True)
+    g = torch.tensor(gains, dtype=torch.float64, device="cuda", requires_grad=True)
+    drag, probe = AdjointRun.apply(prob, a, g)
+    J = prob.objective(drag, probe)
+    J.backward()
+    e_J = abs(float(J) - J_ref) / abs(J_ref)
+    e_a = rel_l2(a.grad.cpu().numpy(), ga_ref)
+    e_g = rel_l2(g.grad.cpu().numpy(), gg_ref)
+    say(f"  J rel err {e_J:.3e}, coeff gradient {e_a:.3e}, gain gradient {e_g:.3e}")
+    assert e_J <= gate and e_a <= gate and e_g <= gate
+
+
+# ---------------------------------------------------------------------------
 # full channel configuration
 # ---------------------------------------------------------------------------
 def test_adjoint_full_channel_vs_gpu_finite_differences():
