@@ -27,7 +27,10 @@ if ROOT not in sys.path:
 METRIC = "MLUPS (D3Q27 ACM-MRT+IBM), % HBM roofline; FP16-store vs FP32 at stated error"
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "k_fused_turbulence256_f32_counters.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2101_11856_amd", "csrc", f) for f in ("lbm_step.hip", "lbm_internal.hpp")]
+# sources that decide the fused kernel's code and memory layout, and its build flags
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2101_11856_amd", "csrc", f)
+                  for f in ("lbm_step.hip", "lbm_internal.hpp", "lbm_api.hip", "lbm_ctx.hpp")]
+KERNEL_SOURCES.append(os.path.join(ROOT, "paper_2101_11856_amd", "build.py"))
 
 
 def log(msg):

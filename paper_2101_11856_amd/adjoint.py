@@ -48,7 +48,7 @@ class ChannelProblem:
         self.solver.set_solids(self.xyz, self.ub, self.area, np.ones(self.n, np.float32))
         self.B = torch.as_tensor(synth.inlet_mode_basis(ny, nz, length=mode_length), dtype=torch.float64,
                                  device=self.device)                     # [16, nz, ny]
-        rho, u = synth.uniform(nx, ny, nz, (base, 0.0, 0.0))
+        rho, u = synth.uniform(nx, ny, nz, (base, 0.0, 0.0), dtype=np.float64)   # rounded to the storage type by the solver
         self._rho0, self._u0 = rho, u
         self.solver.adjoint_init()
 

@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(const AdjParams<ST> P)
             Fz += F.z;
         }
     }
-    const int64_t base = ((int64_t)z * g.ny + y) * g.nxp + xc;
+    const int64_t base = row_off(g, y, z) + xc;
     R lam[3][3][3];
 #pragma unroll
     for (int i = 0; i < Q; ++i) lam[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = P.lam[(int64_t)i * g.plane + base];
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(256) k_adj_band(Geom g, const int32_t *__restr
     const auto ru = band_ru[b];
     const auto bb = band_bar[b];
     const R inv = (R)1 / ru.x;
-    const int64_t base = ((int64_t)z * g.ny + y) * g.nxp + x;
+    const int64_t base = row_off(g, y, z) + x;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const R add = bb.x + (bb.y * ((R)CX[i] - ru.y) + bb.z * ((R)CY[i] - ru.z) + bb.w * ((R)CZ[i] - ru.w)) * inv;
@@ -191,12 +191,12 @@ __global__ void __launch_bounds__(256) k_adj_push(Geom g, const R *__restrict__ 
     int xs, x, y, z;
     node_of_item(g, w, lane, xs, x, y, z);
     if (x >= g.nx) return;
-    const int64_t base = ((int64_t)z * g.ny + y) * g.nxp + x;
+    const int64_t base = row_off(g, y, z) + x;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const R mu = M[(int64_t)i * g.plane + base];
         const PullSrc s = resolve(i, x, y, z, g);
-        unsafeAtomicAdd(lam + (int64_t)s.pl * g.plane + ((int64_t)s.sz * g.ny + s.sy) * g.nxp + s.sx, mu);
+        unsafeAtomicAdd(lam + (int64_t)s.pl * g.plane + row_off(g, s.sy, s.sz) + s.sx, mu);
         if (s.inlet && g_inlet) {
             const double c = 6.0 * weight(i) * (double)mu;
             const int64_t row = (int64_t)s.sz * g.ny + s.sy;
@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(256) k_adj_seed_macros(Geom g, const typename 
     const R u[3] = {m.jx * inv, m.jy * inv, m.jz * inv};
     const R gr = g_rho ? g_rho[k] : (R)0;
     const R gu[3] = {g_u ? g_u[k] : (R)0, g_u ? g_u[N + k] : (R)0, g_u ? g_u[2 * N + k] : (R)0};
-    const int64_t base = ((int64_t)z * g.ny + y) * g.nxp + x;
+    const int64_t base = row_off(g, y, z) + x;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         M[(int64_t)i * g.plane + base] =
@@ -258,7 +258,7 @@ __global__ void k_adj_io(Geom g, R *__restrict__ lam, R *__restrict__ dense, int
     const int x = (int)(k % g.nx);
     const int64_t r = k / g.nx;
     const int y = (int)(r % g.ny), z = (int)(r / g.ny);
-    const int64_t base = ((int64_t)z * g.ny + y) * g.nxp + x;
+    const int64_t base = row_off(g, y, z) + x;
     for (int i = 0; i < Q; ++i) {
         if (to_state) lam[(int64_t)i * g.plane + base] = dense[(int64_t)i * N + k];
         else dense[(int64_t)i * N + k] = lam[(int64_t)i * g.plane + base];
@@ -273,14 +273,14 @@ static inline dim3 g1(int64_t n) { return dim3((unsigned)std::max<int64_t>(1, (n
 
 size_t adjoint_ws_bytes(const lbm_ctx *c)
 {
-    const size_t planes = a256((size_t)Q * c->g.plane * c->rsize);
+    const size_t planes = a256((size_t)c->g.total * c->rsize);
     const size_t band = a256((size_t)std::max<int64_t>(c->nband, 1) * 4 * c->rsize);
     return 3 * planes + 2 * band;
 }
 
 void adjoint_bind(lbm_ctx *c, void *ws, size_t bytes)
 {
-    const size_t planes = a256((size_t)Q * c->g.plane * c->rsize);
+    const size_t planes = a256((size_t)c->g.total * c->rsize);
     const size_t band = a256((size_t)std::max<int64_t>(c->nband, 1) * 4 * c->rsize);
     char *p = static_cast<char *>(ws);
     c->aws = p;
@@ -350,7 +350,7 @@ template <int ST> static hipError_t step_st(lbm_ctx *c, const void *state, doubl
     else hipLaunchKernelGGL((k_adj_collide<ST, false>), grid, block, 0, c->stream, P);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (c->nm > 0 && (e = adj_ib_part<R>(c, g_gain)) != hipSuccess) return e;
-    if ((e = launch_zero(c, c->lam_out, (size_t)Q * c->g.plane * c->rsize)) != hipSuccess) return e;
+    if ((e = launch_zero(c, c->lam_out, (size_t)c->g.total * c->rsize)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_adj_push<R>), grid, block, 0, c->stream, c->g, static_cast<const R *>(c->adjM),
                        static_cast<R *>(c->lam_out), g_inlet);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -378,7 +378,7 @@ template <int ST> static hipError_t seed_force_st(lbm_ctx *c, const double gf[3]
     using R4 = typename V4<R>::type;
     hipError_t e;
     if ((e = launch_band_ib(c, c->fA, c->ftot_eval)) != hipSuccess) return e;
-    if ((e = launch_zero(c, c->adjM, (size_t)Q * c->g.plane * c->rsize)) != hipSuccess) return e;
+    if ((e = launch_zero(c, c->adjM, (size_t)c->g.total * c->rsize)) != hipSuccess) return e;
     // phi = g_force at every band node: the gather sum_d K_d phi then equals g_force
     hipLaunchKernelGGL((k_fill4<R>), g1(c->nband), dim3(256), 0, c->stream, static_cast<R4 *>(c->band_phi), c->nband,
                        (R)gf[0], (R)gf[1], (R)gf[2], (R)0);

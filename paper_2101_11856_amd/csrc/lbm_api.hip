@@ -32,14 +32,22 @@ lbm_status hip_fail(lbm_ctx *c, hipError_t e, const char *where)
 
 bool valid_rate(double s) { return std::isfinite(s) && s > 0.0 && s < 2.0; }
 
-// extra elements between population planes (spreads the 27 concurrent
-// streams over HBM channels); tunable for measurements
-int64_t plane_skew()
+// Rows per population block (a power of two): the largest with at most
+// BLOCK_NODES padded nodes per block, at least 1, at most the row count.
+// LBM_BLOCK_ROWS overrides it for measurements (0 = plain plane-major layout).
+constexpr int64_t BLOCK_NODES = 2048;
+int block_log2_rows(int64_t rows, int64_t nxp)
 {
-    const char *e = std::getenv("LBM_PLANE_SKEW");
-    if (!e) return 0;
-    const long v = std::strtol(e, nullptr, 10);
-    return v > 0 ? (int64_t)v : 0;
+    int64_t want = -1;
+    if (const char *e = std::getenv("LBM_BLOCK_ROWS")) want = std::strtol(e, nullptr, 10);
+    if (want == 0) return 31;
+    int lr = 0;
+    if (want > 0) {
+        while ((int64_t(2) << lr) <= want && (int64_t(2) << lr) <= rows) ++lr;
+        return lr;
+    }
+    while ((int64_t(2) << lr) * nxp <= BLOCK_NODES && (int64_t(2) << lr) <= rows) ++lr;
+    return lr;
 }
 
 lbm_status validate(const lbm_params *p, std::string &err)
@@ -74,8 +82,8 @@ lbm_status validate(const lbm_params *p, std::string &err)
 }
 
 struct Layout {
-    int nxp, ntx;
-    int64_t plane, W, rows;
+    int nxp, ntx, lr;
+    int64_t plane, bstride, pop_elems, W, rows;
     size_t esize, rsize;
     size_t offA, offB, offSA, offSB, offPart, offOut, offFt, offFe, offFlag, total;
     int red_blocks;
@@ -88,12 +96,22 @@ Layout layout(const lbm_params *p)
     L.ntx = (p->nx + SEG - 1) / SEG;
     L.rows = (int64_t)p->ny * p->nz;
     L.W = (int64_t)L.ntx * L.rows;
-    L.plane = (int64_t)align_up((size_t)(L.rows * L.nxp), 64) + plane_skew();
+    L.lr = block_log2_rows(L.rows, L.nxp);
+    if (L.lr == 31) {
+        L.plane = (int64_t)align_up((size_t)(L.rows * L.nxp), 64);
+        L.bstride = 0;
+        L.pop_elems = (int64_t)Q * L.plane;
+    } else {
+        const int64_t R = int64_t(1) << L.lr;
+        L.plane = R * L.nxp;
+        L.bstride = (int64_t)Q * L.plane;
+        L.pop_elems = ((L.rows + R - 1) >> L.lr) * L.bstride;
+    }
     L.esize = p->storage == LBM_F32 ? 4 : p->storage == LBM_F64 ? 8 : 2;
     L.rsize = p->storage == LBM_F64 ? 8 : 4;
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     L.red_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 255) / 256));
-    const size_t fbytes = align_up((size_t)Q * L.plane * L.esize, ALIGN);
+    const size_t fbytes = align_up((size_t)L.pop_elems * L.esize, ALIGN);
     const size_t sbytes = p->passive_scalar ? align_up((size_t)L.rows * L.nxp * 4, ALIGN) : 0;
     size_t o = 0;
     L.offA = o;
@@ -120,7 +138,7 @@ Layout layout(const lbm_params *p)
 
 size_t state_bytes(const lbm_ctx *c)
 {
-    size_t b = (size_t)Q * c->g.plane * c->esize;
+    size_t b = (size_t)c->g.total * c->esize;
     if (c->p.passive_scalar) b += (size_t)c->rows * c->g.nxp * 4;
     return b;
 }
@@ -180,13 +198,17 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, voi
     if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
     c->p = *p;
     c->stream = static_cast<hipStream_t>(hip_stream);
-    hipGetDevice(&c->device);
+    (void)hipGetDevice(&c->device);
     c->g.nx = p->nx;
     c->g.ny = p->ny;
     c->g.nz = p->nz;
     c->g.nxp = L.nxp;
     c->g.ntx = L.ntx;
+    c->g.lr = L.lr;
+    c->g.rmask = L.lr == 31 ? (int64_t)0x7fffffff : (int64_t(1) << L.lr) - 1;
     c->g.plane = L.plane;
+    c->g.bstride = L.bstride;
+    c->g.total = L.pop_elems;
     c->g.W = L.W;
     for (int f = 0; f < 6; ++f) c->g.face[f] = p->face[f];
     c->N = (int64_t)p->nx * p->ny * p->nz;
@@ -393,7 +415,7 @@ lbm_status lbm_checkpoint(lbm_ctx *c, void *dst)
 {
     CHECK_CTX(c);
     if (!dst) return fail(c, LBM_E_INVAL, "dst is NULL");
-    const size_t fb = (size_t)Q * c->g.plane * c->esize;
+    const size_t fb = (size_t)c->g.total * c->esize;
     HIP_TRY(c, launch_copy(c, dst, c->fA, fb), "lbm_checkpoint");
     if (c->p.passive_scalar)
         HIP_TRY(c, launch_copy(c, static_cast<char *>(dst) + fb, c->scA, (size_t)c->rows * c->g.nxp * 4),
@@ -405,7 +427,7 @@ lbm_status lbm_restore(lbm_ctx *c, const void *src)
 {
     CHECK_CTX(c);
     if (!src) return fail(c, LBM_E_INVAL, "src is NULL");
-    const size_t fb = (size_t)Q * c->g.plane * c->esize;
+    const size_t fb = (size_t)c->g.total * c->esize;
     HIP_TRY(c, launch_copy(c, c->fA, src, fb), "lbm_restore");
     if (c->p.passive_scalar)
         HIP_TRY(c, launch_copy(c, c->scA, static_cast<const char *>(src) + fb, (size_t)c->rows * c->g.nxp * 4),
@@ -452,7 +474,7 @@ lbm_status lbm_adjoint_init(lbm_ctx *c, void *adj_ws, size_t bytes)
     if (bytes < adjoint_ws_bytes(c))
         return fail(c, LBM_E_NOMEM, "adjoint workspace too small: need " + std::to_string(adjoint_ws_bytes(c)) + " bytes");
     adjoint_bind(c, adj_ws, bytes);
-    HIP_TRY(c, launch_zero(c, c->lam_in, (size_t)Q * c->g.plane * c->rsize), "lbm_adjoint_init");
+    HIP_TRY(c, launch_zero(c, c->lam_in, (size_t)c->g.total * c->rsize), "lbm_adjoint_init");
     return LBM_OK;
 }
 

@@ -16,10 +16,13 @@ __device__ __forceinline__ void cell_coords(int64_t k, const Geom &g, int &x, in
     y = (int)(r % g.ny);
     z = (int)(r / g.ny);
 }
+// scalar field: one plane [rows][nxp]
 __device__ __forceinline__ int64_t padded(int x, int y, int z, const Geom &g)
 {
     return ((int64_t)z * g.ny + y) * g.nxp + x;
 }
+// population 0 of node (x, y, z) in the blocked population layout
+__device__ __forceinline__ int64_t pop_node(int x, int y, int z, const Geom &g) { return row_off(g, y, z) + x; }
 
 // ---------------------------------------------------------------------------
 // equilibrium: d_i = rho (prod phi(u) - prod phi(0)) + (rho - 1) w_i with the
@@ -46,7 +49,7 @@ __global__ void k_init_eq(Geom g, const RR<ST> *__restrict__ rho, const RR<ST> *
         d[a][1] = -v2;
         d[a][2] = (R)0.5 * (v2 + v);
     }
-    const int64_t base = padded(x, y, z, g);
+    const int64_t base = pop_node(x, y, z, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = CX[i] + 1, cy = CY[i] + 1, cz = CZ[i] + 1;
@@ -66,7 +69,7 @@ __global__ void k_set_pop(Geom g, const RR<ST> *__restrict__ src, TT<ST> *__rest
     if (k >= N) return;
     int x, y, z;
     cell_coords(k, g, x, y, z);
-    const int64_t base = padded(x, y, z, g);
+    const int64_t base = pop_node(x, y, z, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         f[(int64_t)i * g.plane + base] = Store<ST>::enc(src[(int64_t)i * N + k] - (RR<ST>)weight(i));
@@ -79,7 +82,7 @@ __global__ void k_get_pop(Geom g, const TT<ST> *__restrict__ f, RR<ST> *__restri
     if (k >= N) return;
     int x, y, z;
     cell_coords(k, g, x, y, z);
-    const int64_t base = padded(x, y, z, g);
+    const int64_t base = pop_node(x, y, z, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         dst[(int64_t)i * N + k] = Store<ST>::dec(f[(int64_t)i * g.plane + base]) + (RR<ST>)weight(i);
@@ -119,7 +122,7 @@ __global__ void __launch_bounds__(256) k_conserved(Geom g, const TT<ST> *__restr
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x) {
         int x, y, z;
         cell_coords(k, g, x, y, z);
-        const int64_t base = padded(x, y, z, g);
+        const int64_t base = pop_node(x, y, z, g);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const double v = (double)Store<ST>::dec(f[(int64_t)i * g.plane + base]);

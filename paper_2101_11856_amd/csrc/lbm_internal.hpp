@@ -122,14 +122,34 @@ template <typename T> __device__ __forceinline__ T ld_stream(const T *p)
 #endif
 }
 
+// Population layout.  Rows (row = z*ny + y) are grouped into blocks of
+// R = 2^lr rows stored as [block][27][R][nxp]: population i of node (x, row)
+// sits at (row >> lr) * bstride + i * plane + (row & rmask) * nxp + x, with
+// plane = R*nxp and bstride = 27*R*nxp.  Each block is one contiguous region,
+// so a wave's 27 loads (and 27 stores) fall in a few nearby DRAM pages instead
+// of 27 distant planes.  lr = 31 is the plain plane-major layout [27][rows][nxp]
+// (one block; plane = padded rows*nxp).
 struct Geom {
     int nx, ny, nz;
-    int nxp;        // row pitch (elements), multiple of 32
-    int ntx;        // segments per row
-    int64_t plane;  // plane stride (elements)
-    int64_t W;      // number of work items
+    int nxp;         // row pitch (elements), multiple of 32
+    int ntx;         // segments per row
+    int lr;          // log2 of the rows per block
+    int64_t rmask;   // rows per block - 1
+    int64_t plane;   // stride between populations inside a block (elements)
+    int64_t bstride; // stride between blocks (elements)
+    int64_t total;   // elements of one population copy
+    int64_t W;       // number of work items
     int face[6];
 };
+
+__host__ __device__ __forceinline__ int64_t row_off(const Geom &g, int64_t row)
+{
+    return (row >> g.lr) * g.bstride + (row & g.rmask) * g.nxp;
+}
+__host__ __device__ __forceinline__ int64_t row_off(const Geom &g, int y, int z)
+{
+    return row_off(g, (int64_t)z * g.ny + y);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  The remap gives each
 // XCD a contiguous range of logical blocks, so that x-neighbouring segments
@@ -234,7 +254,7 @@ __device__ __forceinline__ R pull_one(int i, const typename Store<ST>::T *__rest
                                       const Geom &g, const Inlet<R> &inl)
 {
     const PullSrc s = resolve(i, x, y, z, g);
-    const int64_t idx = (int64_t)s.pl * g.plane + ((int64_t)s.sz * g.ny + s.sy) * g.nxp + s.sx;
+    const int64_t idx = (int64_t)s.pl * g.plane + row_off(g, s.sy, s.sz) + s.sx;
     R v = Store<ST>::dec(ld_stream(in + idx));
     if (s.inlet) {
         const R cu = (R)CX[i] * inl.at(0, s.sy, s.sz, g.ny, g.nz) + (R)CY[i] * inl.at(1, s.sy, s.sz, g.ny, g.nz) +
@@ -270,18 +290,14 @@ __device__ __forceinline__ void pull_interior(R (&f)[3][3][3], const typename St
     const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-    // per-lane 32-bit offsets; plane and row bases are wave-uniform, so each
-    // load is a scalar base plus a 32-bit vector offset (no 64-bit VALU math)
-    using T = typename Store<ST>::T;
-    const uint32_t xs[3] = {(uint32_t)(xp * sizeof(T)), (uint32_t)(x * sizeof(T)),
-                            (uint32_t)(xm * sizeof(T))};  // byte offset of source x for c_x = -1, 0, +1
+    const int xs[3] = {xp, x, xm};  // source x for c_x = -1, 0, +1
     const int ys[3] = {yp, y, ym};
     const int zs[3] = {zp, z, zm};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int64_t row = ((int64_t)zs[CZ[i] + 1] * g.ny + ys[CY[i] + 1]) * g.nxp;
-        const T *pl = in + ((int64_t)i * g.plane + row);
-        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(ld_stream(at_bytes(pl, xs[CX[i] + 1])));
+        const int64_t row = row_off(g, ys[CY[i] + 1], zs[CZ[i] + 1]);
+        const typename Store<ST>::T *pl = in + (int64_t)i * g.plane + row;
+        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(ld_stream(pl + xs[CX[i] + 1]));
     }
 }
 
@@ -301,7 +317,7 @@ __device__ __forceinline__ void pull_xface(R (&f)[3][3][3], const typename Store
     const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
     const int ys[3] = {yp, y, ym};
     const int zs[3] = {zp, z, zm};
-    const int64_t row_own = ((int64_t)z * g.ny + y) * g.nxp;
+    const int64_t row_own = row_off(g, y, z);
     const int F0 = g.face[0], F1 = g.face[1];
     const bool lo = x == 0, hi = x == g.nx - 1;
     const R uin[3] = {inl.at(0, y, z, g.ny, g.nz), inl.at(1, y, z, g.ny, g.nz), inl.at(2, y, z, g.ny, g.nz)};
@@ -309,7 +325,7 @@ __device__ __forceinline__ void pull_xface(R (&f)[3][3][3], const typename Store
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = CX[i];
-        const int64_t row_src = ((int64_t)zs[CZ[i] + 1] * g.ny + ys[CY[i] + 1]) * g.nxp;
+        const int64_t row_src = row_off(g, ys[CY[i] + 1], zs[CZ[i] + 1]);
         const T *nb = in + ((int64_t)i * g.plane + row_src);
         R v;
         if (cx == 0) {

@@ -100,12 +100,11 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     R rho, ux, uy, uz;
     collide(f, Fx, Fy, Fz, P.rt, rho, ux, uy, uz);
     if (active) {
-        const int64_t row = ((int64_t)z * g.ny + y) * g.nxp;  // wave-uniform
-        const uint32_t xb = (uint32_t)(x * sizeof(typename Store<ST>::T));
+        const int64_t base = row_off(g, y, z) + x;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             __builtin_nontemporal_store(Store<ST>::enc(f[CZ[i] + 1][CY[i] + 1][CX[i] + 1]),
-                                        at_bytes(P.fout + ((int64_t)i * g.plane + row), xb));
+                                        P.fout + (int64_t)i * g.plane + base);
     }
     if (SCALAR) scalar_update<ST>(P, xc, y, z, (float)ux, (float)uy, (float)uz, active);
 }

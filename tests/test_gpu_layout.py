@@ -1,0 +1,62 @@
+"""The population layout (rows per block, or the plain plane-major form) is a
+storage choice only: every layout runs the same arithmetic in the same order,
+so all results must be bit-identical across layouts.  Exercised on a channel
+with every face rule, immersed samples, an inlet profile and the passive
+scalar, in FP32 and FP16 storage, on a grid whose row count is not a multiple
+of the block height (ragged last block)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2101_11856_amd import synth
+from tests.gpu_cases import FS, IN, NS, OUT, P, say
+from tests.test_gpu_parity import _ib_scene, _inlet
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (70, 18, 15)          # nx, ny, nz: 270 rows, nx padded to 96
+FACES = (IN, OUT, NS, FS, P, P)
+LAYOUTS = ["0", "1", "2", "8", None]   # plane-major, 1/2/8 rows per block, default
+
+
+def _run(storage, rows, monkeypatch):
+    from paper_2101_11856_amd import lbm
+    if rows is None:
+        monkeypatch.delenv("LBM_BLOCK_ROWS", raising=False)
+    else:
+        monkeypatch.setenv("LBM_BLOCK_ROWS", rows)
+    nx, ny, nz = SHAPE
+    s = lbm.Solver(nx, ny, nz, 0.02, faces=FACES, inlet_profile=_inlet(ny, nz), storage=storage, scalar=True,
+                   scalar_inlet_height=6)
+    xyz, ub, area, gain = _ib_scene(nx, ny, nz, 11)
+    s.set_solids(xyz, ub, area, gain)
+    rho, u = synth.uniform(nx, ny, nz, (0.04, 0.0, 0.0))
+    s.init_equilibrium(rho, u)
+    s.step(25)
+    out = dict(f=s.get_populations().cpu(), scalar=s.get_scalar().cpu())
+    r, v = s.macros()
+    out["rho"], out["u"] = r.cpu(), v.cpu()
+    out["force"] = np.asarray(s.ib_force())
+    out["mass"] = np.asarray(s.conserved())
+    snap = s.checkpoint()
+    s.step(3)
+    after = s.get_populations().cpu()
+    s.restore(snap)
+    s.step(3)
+    out["replay_equal"] = bool(torch.equal(after, s.get_populations().cpu()))
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_layouts_are_bit_identical(storage, monkeypatch):
+    say(f"layout invariance, {SHAPE}, storage={storage}")
+    ref = _run(storage, "0", monkeypatch)
+    assert ref["replay_equal"]
+    for rows in LAYOUTS[1:]:
+        o = _run(storage, rows, monkeypatch)
+        say(f"  rows per block={rows or 'default'}")
+        for k in ("f", "scalar", "rho", "u"):
+            assert torch.equal(o[k], ref[k]), (rows, k)
+        assert np.array_equal(o["force"], ref["force"]) and np.array_equal(o["mass"], ref["mass"]), rows
+        assert o["replay_equal"], rows
