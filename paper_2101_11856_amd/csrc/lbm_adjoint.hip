@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(const AdjParams<ST> P)
     const bool active = x < g.nx;
     const int xc = active ? x : g.nx - 1;
     R f[3][3][3];
-    pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
+    pull_wave<ST, false>(f, P.fin, 0u, xs, xc, y, z, g, P.inlet);
     R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
     int slot = -1;
     if (BAND) {

@@ -209,12 +209,21 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, voi
     c->g.plane = L.plane;
     c->g.bstride = L.bstride;
     c->g.total = L.pop_elems;
+    c->g.dntx = make_divisor((uint32_t)L.ntx);
+    c->g.dny = make_divisor((uint32_t)p->ny);
     c->g.W = L.W;
     for (int f = 0; f < 6; ++f) c->g.face[f] = p->face[f];
     c->N = (int64_t)p->nx * p->ny * p->nz;
     c->rows = L.rows;
     c->esize = L.esize;
     c->rsize = L.rsize;
+    // 32-bit buffer addressing in the fused kernel when a copy fits below 2^31
+    // bytes (FP64 keeps pointers); LBM_POINTER_PATH=1 forces pointers (measurements)
+    {
+        const char *e = std::getenv("LBM_POINTER_PATH");
+        const bool force_ptr = e && std::strtol(e, nullptr, 10) != 0;
+        c->buffer_path = !force_ptr && p->storage != LBM_F64 && (uint64_t)L.pop_elems * L.esize < (uint64_t(1) << 31);
+    }
     c->ws = static_cast<char *>(workspace);
     c->ws_bytes = ws_bytes;
     c->fA = c->ws + L.offA;

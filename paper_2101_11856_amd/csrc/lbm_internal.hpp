@@ -84,7 +84,7 @@ template <> struct Store<LBM_BF16DEV> {
 // geometry shared by every kernel
 // ---------------------------------------------------------------------------
 
-// Build-time tuning switches (measured; see the design notes for the values).
+// Build-time tuning switches (values chosen by measurement on MI355X).
 #ifndef LBM_NT_LOADS
 #define LBM_NT_LOADS 0      // population reads with the non-temporal (streaming) hint
 #endif
@@ -93,6 +93,12 @@ template <> struct Store<LBM_BF16DEV> {
 #endif
 #ifndef LBM_XCD_REMAP
 #define LBM_XCD_REMAP 0     // contiguous logical blocks per XCD (off: all XCDs share one moving front)
+#endif
+#ifndef LBM_BUF_LOADS
+#define LBM_BUF_LOADS 0     // interior pull through buffer descriptors when a copy is below 2^31 bytes
+#endif                      // (off: measured 1-2% slower than pointer loads in FP32 and FP16)
+#ifndef LBM_BUF_STORES
+#define LBM_BUF_STORES 1    // stores through buffer descriptors when a copy is below 2^31 bytes
 #endif
 
 // Work item = one x-segment of 64 nodes of one (y, z) row; a wavefront owns
@@ -129,6 +135,27 @@ template <typename T> __device__ __forceinline__ T ld_stream(const T *p)
 // so a wave's 27 loads (and 27 stores) fall in a few nearby DRAM pages instead
 // of 27 distant planes.  lr = 31 is the plain plane-major layout [27][rows][nxp]
 // (one block; plane = padded rows*nxp).
+// Division by an invariant divisor d (1 <= d < 2^31) of numerators n < 2^31:
+// q = (n * m) >> (31 + l) with l = ceil(log2 d) and m = ceil(2^(31+l) / d).
+// m = (2^(31+l) + e) / d with 0 <= e < d <= 2^l, so n*m / 2^(31+l) exceeds n/d
+// by less than n*e / (d 2^(31+l)) < 1/d: the floor is exact (the round-up
+// method for invariant divisors).  m <= 2^32 + 1, so n*m fits in 64 bits.
+struct Divisor {
+    uint64_t m;
+    int sh;
+};
+inline Divisor make_divisor(uint32_t d)
+{
+    int l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    const uint64_t p = uint64_t(1) << (31 + l);
+    return {p / d + (p % d != 0), 31 + l};
+}
+__host__ __device__ __forceinline__ uint32_t divide(uint32_t n, const Divisor &d)
+{
+    return (uint32_t)(((uint64_t)n * d.m) >> d.sh);
+}
+
 struct Geom {
     int nx, ny, nz;
     int nxp;         // row pitch (elements), multiple of 32
@@ -138,9 +165,20 @@ struct Geom {
     int64_t plane;   // stride between populations inside a block (elements)
     int64_t bstride; // stride between blocks (elements)
     int64_t total;   // elements of one population copy
-    int64_t W;       // number of work items
+    int64_t W;       // number of work items (< 2^31)
+    Divisor dntx, dny;
     int face[6];
 };
+
+// work item w -> (segment, y, z); all three are wave-uniform
+__device__ __forceinline__ void wave_coords(uint32_t w, const Geom &g, int &xs, int &y, int &z)
+{
+    const uint32_t row = divide(w, g.dntx);
+    xs = (int)(w - row * (uint32_t)g.ntx);
+    const uint32_t zz = divide(row, g.dny);
+    y = (int)(row - zz * (uint32_t)g.ny);
+    z = (int)zz;
+}
 
 __host__ __device__ __forceinline__ int64_t row_off(const Geom &g, int64_t row)
 {
@@ -149,6 +187,41 @@ __host__ __device__ __forceinline__ int64_t row_off(const Geom &g, int64_t row)
 __host__ __device__ __forceinline__ int64_t row_off(const Geom &g, int y, int z)
 {
     return row_off(g, (int64_t)z * g.ny + y);
+}
+
+// The same offset in 32 bits, for population copies below 2^31 bytes.
+__device__ __forceinline__ uint32_t row_off32(const Geom &g, uint32_t row)
+{
+    return (row >> g.lr) * (uint32_t)g.bstride + (row & (uint32_t)g.rmask) * (uint32_t)g.nxp;
+}
+
+// Raw buffer access to a population copy below 2^31 bytes: the wave-uniform
+// part of an offset goes in a scalar register (soffset), the per-lane part in
+// a 32-bit vector register, so an access costs no vector address arithmetic.
+// Descriptor word 3 is the gfx9 raw-buffer format (32-bit data format).
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ BufRsrc make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buf_ld(BufRsrc r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float buf_ld<float>(BufRsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ uint16_t buf_ld<uint16_t>(BufRsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+}
+// non-temporal store (aux bit 1 = nt)
+template <typename T> __device__ __forceinline__ void buf_st_nt(T v, BufRsrc r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ void buf_st_nt<float>(float v, BufRsrc r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 2);
+}
+template <> __device__ __forceinline__ void buf_st_nt<uint16_t>(uint16_t v, BufRsrc r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)voff, (int)soff, 2);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  The remap gives each
@@ -301,6 +374,26 @@ __device__ __forceinline__ void pull_interior(R (&f)[3][3][3], const typename St
     }
 }
 
+// The interior pull through a buffer descriptor (copies below 2^31 bytes).
+template <int ST, typename R>
+__device__ __forceinline__ void pull_interior_buf(R (&f)[3][3][3], BufRsrc in, int x, int y, int z, const Geom &g)
+{
+    using T = typename Store<ST>::T;
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    const uint32_t xs[3] = {(uint32_t)(xp * sizeof(T)), (uint32_t)(x * sizeof(T)),
+                            (uint32_t)(xm * sizeof(T))};  // byte offset of source x for c_x = -1, 0, +1
+    const int ys[3] = {yp, y, ym};
+    const int zs[3] = {zp, z, zm};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const uint32_t row = (uint32_t)(zs[CZ[i] + 1] * g.ny + ys[CY[i] + 1]);
+        const uint32_t u = ((uint32_t)i * (uint32_t)g.plane + row_off32(g, row)) * (uint32_t)sizeof(T);
+        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(buf_ld<T>(in, xs[CX[i] + 1], u));
+    }
+}
+
 // Pull for a wave that touches a non-periodic x face but no y or z face (an
 // x-segment at either end of a row).  Directions with c_x = 0 read as in the
 // interior.  The others select per lane between the plain source and the face
@@ -350,15 +443,18 @@ __device__ __forceinline__ void pull_xface(R (&f)[3][3][3], const typename Store
 
 // Wave-level choice of the pull (all lanes of a wave share y, z and the
 // segment): the face-aware general form only for rows on a y or z face.
-template <int ST, typename R>
-__device__ __forceinline__ void pull_wave(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int xs, int x,
-                                          int y, int z, const Geom &g, const Inlet<R> &inl)
+// With B32 the interior form reads through a buffer descriptor over the
+// `bytes` of the copy (below 2^31); the face forms always use plain pointers.
+template <int ST, bool B32, typename R>
+__device__ __forceinline__ void pull_wave(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, uint32_t bytes,
+                                          int xs, int x, int y, int z, const Geom &g, const Inlet<R> &inl)
 {
     const bool yz = (y == 0 && g.face[2] != LBM_PERIODIC) || (y == g.ny - 1 && g.face[3] != LBM_PERIODIC) ||
                     (z == 0 && g.face[4] != LBM_PERIODIC) || (z == g.nz - 1 && g.face[5] != LBM_PERIODIC);
     const bool xf = (xs == 0 && g.face[0] != LBM_PERIODIC) || (xs == g.ntx - 1 && g.face[1] != LBM_PERIODIC);
     if (yz) pull_general<ST>(f, in, x, y, z, g, inl);
     else if (xf) pull_xface<ST>(f, in, x, y, z, g, inl);
+    else if constexpr (B32 && LBM_BUF_LOADS) pull_interior_buf<ST>(f, make_rsrc(in, bytes), x, y, z, g);
     else pull_interior<ST>(f, in, x, y, z, g);
 }
 

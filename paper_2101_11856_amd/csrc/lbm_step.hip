@@ -67,24 +67,29 @@ __device__ __forceinline__ void scalar_update(const StepParams<ST> &P, int x, in
 // ---------------------------------------------------------------------------
 // fused step
 // ---------------------------------------------------------------------------
-template <int ST, bool BAND, bool SCALAR>
+// B32: both population copies are below 2^31 bytes, so every offset is a
+// 32-bit value and interior loads and all stores go through buffer
+// descriptors (uniform part in a scalar register, no 64-bit vector address
+// arithmetic).
+template <int ST, bool BAND, bool SCALAR, bool B32>
 __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams<ST> P)
 {
     using R = typename Store<ST>::R;
+    using T = typename Store<ST>::T;
     const Geom &g = P.g;
     const int lane = threadIdx.x & (SEG - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / SEG);
-    const int64_t w = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + wv;
-    if (w >= g.W) return;
-    const int xs = (int)(w % g.ntx);
-    const int64_t row = w / g.ntx;
-    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    const uint32_t w = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (uint32_t)wv;
+    if (w >= (uint32_t)g.W) return;
+    int xs, y, z;
+    wave_coords(w, g, xs, y, z);
     const int x = xs * SEG + lane;
     const bool active = x < g.nx;
     const int xc = active ? x : g.nx - 1;
+    const uint32_t bytes = (uint32_t)(g.total * (int64_t)sizeof(T));
 
     R f[3][3][3];
-    pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
+    pull_wave<ST, B32>(f, P.fin, bytes, xs, xc, y, z, g, P.inlet);
 
     R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
     if (BAND) {
@@ -100,11 +105,21 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     R rho, ux, uy, uz;
     collide(f, Fx, Fy, Fz, P.rt, rho, ux, uy, uz);
     if (active) {
-        const int64_t base = row_off(g, y, z) + x;
+        if constexpr (B32 && LBM_BUF_STORES) {
+            const BufRsrc rout = make_rsrc(P.fout, bytes);
+            const uint32_t ro = row_off32(g, (uint32_t)(z * g.ny + y));
+            const uint32_t xb = (uint32_t)(x * sizeof(T));
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            __builtin_nontemporal_store(Store<ST>::enc(f[CZ[i] + 1][CY[i] + 1][CX[i] + 1]),
-                                        P.fout + (int64_t)i * g.plane + base);
+            for (int i = 0; i < Q; ++i)
+                buf_st_nt<T>(Store<ST>::enc(f[CZ[i] + 1][CY[i] + 1][CX[i] + 1]), rout, xb,
+                             ((uint32_t)i * (uint32_t)g.plane + ro) * (uint32_t)sizeof(T));
+        } else {
+            const int64_t base = row_off(g, y, z) + x;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                __builtin_nontemporal_store(Store<ST>::enc(f[CZ[i] + 1][CY[i] + 1][CX[i] + 1]),
+                                            P.fout + (int64_t)i * g.plane + base);
+        }
     }
     if (SCALAR) scalar_update<ST>(P, xc, y, z, (float)ux, (float)uy, (float)uz, active);
 }
@@ -302,15 +317,25 @@ template <int ST> StepParams<ST> make_params(lbm_ctx *c)
 
 static inline unsigned blocks_for_items(int64_t W) { return (unsigned)((W + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK); }
 
+template <int ST, bool B32> static void fused_launch(lbm_ctx *c, const StepParams<ST> &P)
+{
+    const bool band = c->nm > 0, scalar = c->p.passive_scalar != 0;
+    const dim3 grid(blocks_for_items(c->g.W)), block(SEG * WAVES_PER_BLOCK);
+    if (band && scalar) hipLaunchKernelGGL((k_fused<ST, true, true, B32>), grid, block, 0, c->stream, P);
+    else if (band) hipLaunchKernelGGL((k_fused<ST, true, false, B32>), grid, block, 0, c->stream, P);
+    else if (scalar) hipLaunchKernelGGL((k_fused<ST, false, true, B32>), grid, block, 0, c->stream, P);
+    else hipLaunchKernelGGL((k_fused<ST, false, false, B32>), grid, block, 0, c->stream, P);
+}
+
 template <int ST> static hipError_t fused_st(lbm_ctx *c)
 {
     const StepParams<ST> P = make_params<ST>(c);
-    const bool band = c->nm > 0, scalar = c->p.passive_scalar != 0;
-    const dim3 grid(blocks_for_items(c->g.W)), block(SEG * WAVES_PER_BLOCK);
-    if (band && scalar) hipLaunchKernelGGL((k_fused<ST, true, true>), grid, block, 0, c->stream, P);
-    else if (band) hipLaunchKernelGGL((k_fused<ST, true, false>), grid, block, 0, c->stream, P);
-    else if (scalar) hipLaunchKernelGGL((k_fused<ST, false, true>), grid, block, 0, c->stream, P);
-    else hipLaunchKernelGGL((k_fused<ST, false, false>), grid, block, 0, c->stream, P);
+    if constexpr (ST != LBM_F64) {
+        if (c->buffer_path) fused_launch<ST, true>(c, P);
+        else fused_launch<ST, false>(c, P);
+    } else {
+        fused_launch<ST, false>(c, P);
+    }
     return hipGetLastError();
 }
 
