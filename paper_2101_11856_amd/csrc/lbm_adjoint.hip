@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) k_adj_collide(const AdjParams<ST> P)
     const bool active = x < g.nx;
     const int xc = active ? x : g.nx - 1;
     R f[3][3][3];
-    pull_wave<ST, false>(f, P.fin, 0u, xs, xc, y, z, g, P.inlet);
+    pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
     R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
     int slot = -1;
     if (BAND) {
@@ -222,9 +222,7 @@ __global__ void __launch_bounds__(256) k_adj_seed_macros(Geom g, const typename 
     const int x = (int)(k % g.nx);
     const int64_t r = k / g.nx;
     const int y = (int)(r % g.ny), z = (int)(r / g.ny);
-    R f[3][3][3];
-    pull_node<ST>(f, fin, x, y, z, g, inl);
-    const Macro<R> m = moments01(f);
+    const Macro<R> m = node_moments<ST>(fin, x, y, z, g, inl);
     const R rho = (R)1 + m.drho, inv = (R)1 / rho;
     const R u[3] = {m.jx * inv, m.jy * inv, m.jz * inv};
     const R gr = g_rho ? g_rho[k] : (R)0;

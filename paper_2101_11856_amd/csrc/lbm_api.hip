@@ -217,12 +217,14 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, voi
     c->rows = L.rows;
     c->esize = L.esize;
     c->rsize = L.rsize;
-    // 32-bit buffer addressing in the fused kernel when a copy fits below 2^31
-    // bytes (FP64 keeps pointers); LBM_POINTER_PATH=1 forces pointers (measurements)
+    // per-row buffer descriptors for the fused kernel's stores when the 27
+    // populations of a row span less than 2^31 bytes (always for the blocked
+    // layout; FP64 keeps pointers); LBM_POINTER_PATH=1 forces pointers
     {
         const char *e = std::getenv("LBM_POINTER_PATH");
         const bool force_ptr = e && std::strtol(e, nullptr, 10) != 0;
-        c->buffer_path = !force_ptr && p->storage != LBM_F64 && (uint64_t)L.pop_elems * L.esize < (uint64_t(1) << 31);
+        c->buffer_path = !force_ptr && p->storage != LBM_F64 &&
+                         (uint64_t)Q * (uint64_t)L.plane * L.esize < (uint64_t(1) << 31);
     }
     c->ws = static_cast<char *>(workspace);
     c->ws_bytes = ws_bytes;

@@ -98,9 +98,7 @@ __global__ void k_macros(Geom g, const TT<ST> *__restrict__ f, Inlet<RR<ST>> inl
     if (k >= N) return;
     int x, y, z;
     cell_coords(k, g, x, y, z);
-    R v[3][3][3];
-    pull_node<ST>(v, f, x, y, z, g, inl);
-    const Macro<R> m = moments01(v);
+    const Macro<R> m = node_moments<ST>(f, x, y, z, g, inl);
     const R r = (R)1 + m.drho;
     rho[k] = r;
     u[k] = m.jx / r;

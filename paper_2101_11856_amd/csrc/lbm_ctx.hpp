@@ -19,7 +19,7 @@ struct lbm_ctx {
     int64_t rows = 0;      // ny*nz
     size_t esize = 4;      // bytes per stored population
     size_t rsize = 4;      // bytes of the arithmetic type
-    bool buffer_path = false;  // fused kernel addresses each copy with 32-bit offsets (copy < 2^31 bytes)
+    bool buffer_path = false;  // fused kernel stores through per-row buffer descriptors
     // caller workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;

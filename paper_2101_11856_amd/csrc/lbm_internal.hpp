@@ -94,11 +94,8 @@ template <> struct Store<LBM_BF16DEV> {
 #ifndef LBM_XCD_REMAP
 #define LBM_XCD_REMAP 0     // contiguous logical blocks per XCD (off: all XCDs share one moving front)
 #endif
-#ifndef LBM_BUF_LOADS
-#define LBM_BUF_LOADS 0     // interior pull through buffer descriptors when a copy is below 2^31 bytes
-#endif                      // (off: measured 1-2% slower than pointer loads in FP32 and FP16)
 #ifndef LBM_BUF_STORES
-#define LBM_BUF_STORES 1    // stores through buffer descriptors when a copy is below 2^31 bytes
+#define LBM_BUF_STORES 1    // fused-kernel stores through a per-row buffer descriptor
 #endif
 
 // Work item = one x-segment of 64 nodes of one (y, z) row; a wavefront owns
@@ -189,29 +186,14 @@ __host__ __device__ __forceinline__ int64_t row_off(const Geom &g, int y, int z)
     return row_off(g, (int64_t)z * g.ny + y);
 }
 
-// The same offset in 32 bits, for population copies below 2^31 bytes.
-__device__ __forceinline__ uint32_t row_off32(const Geom &g, uint32_t row)
-{
-    return (row >> g.lr) * (uint32_t)g.bstride + (row & (uint32_t)g.rmask) * (uint32_t)g.nxp;
-}
-
-// Raw buffer access to a population copy below 2^31 bytes: the wave-uniform
-// part of an offset goes in a scalar register (soffset), the per-lane part in
-// a 32-bit vector register, so an access costs no vector address arithmetic.
-// Descriptor word 3 is the gfx9 raw-buffer format (32-bit data format).
+// Raw buffer access: the descriptor holds a wave-uniform 64-bit base, the
+// uniform part of an offset goes in a scalar register (soffset) and the
+// per-lane part in a 32-bit vector register, so an access costs no vector
+// address arithmetic.  Descriptor word 3 is the gfx9 raw-buffer format.
 using BufRsrc = __amdgpu_buffer_rsrc_t;
 __device__ __forceinline__ BufRsrc make_rsrc(const void *base, uint32_t bytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
-}
-template <typename T> __device__ __forceinline__ T buf_ld(BufRsrc r, uint32_t voff, uint32_t soff);
-template <> __device__ __forceinline__ float buf_ld<float>(BufRsrc r, uint32_t voff, uint32_t soff)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
-template <> __device__ __forceinline__ uint16_t buf_ld<uint16_t>(BufRsrc r, uint32_t voff, uint32_t soff)
-{
-    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
 }
 // non-temporal store (aux bit 1 = nt)
 template <typename T> __device__ __forceinline__ void buf_st_nt(T v, BufRsrc r, uint32_t voff, uint32_t soff);
@@ -374,26 +356,6 @@ __device__ __forceinline__ void pull_interior(R (&f)[3][3][3], const typename St
     }
 }
 
-// The interior pull through a buffer descriptor (copies below 2^31 bytes).
-template <int ST, typename R>
-__device__ __forceinline__ void pull_interior_buf(R (&f)[3][3][3], BufRsrc in, int x, int y, int z, const Geom &g)
-{
-    using T = typename Store<ST>::T;
-    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-    const uint32_t xs[3] = {(uint32_t)(xp * sizeof(T)), (uint32_t)(x * sizeof(T)),
-                            (uint32_t)(xm * sizeof(T))};  // byte offset of source x for c_x = -1, 0, +1
-    const int ys[3] = {yp, y, ym};
-    const int zs[3] = {zp, z, zm};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const uint32_t row = (uint32_t)(zs[CZ[i] + 1] * g.ny + ys[CY[i] + 1]);
-        const uint32_t u = ((uint32_t)i * (uint32_t)g.plane + row_off32(g, row)) * (uint32_t)sizeof(T);
-        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(buf_ld<T>(in, xs[CX[i] + 1], u));
-    }
-}
-
 // Pull for a wave that touches a non-periodic x face but no y or z face (an
 // x-segment at either end of a row).  Directions with c_x = 0 read as in the
 // interior.  The others select per lane between the plain source and the face
@@ -443,34 +405,18 @@ __device__ __forceinline__ void pull_xface(R (&f)[3][3][3], const typename Store
 
 // Wave-level choice of the pull (all lanes of a wave share y, z and the
 // segment): the face-aware general form only for rows on a y or z face.
-// With B32 the interior form reads through a buffer descriptor over the
-// `bytes` of the copy (below 2^31); the face forms always use plain pointers.
-template <int ST, bool B32, typename R>
-__device__ __forceinline__ void pull_wave(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, uint32_t bytes,
-                                          int xs, int x, int y, int z, const Geom &g, const Inlet<R> &inl)
+template <int ST, typename R>
+__device__ __forceinline__ void pull_wave(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int xs, int x,
+                                          int y, int z, const Geom &g, const Inlet<R> &inl)
 {
     const bool yz = (y == 0 && g.face[2] != LBM_PERIODIC) || (y == g.ny - 1 && g.face[3] != LBM_PERIODIC) ||
                     (z == 0 && g.face[4] != LBM_PERIODIC) || (z == g.nz - 1 && g.face[5] != LBM_PERIODIC);
     const bool xf = (xs == 0 && g.face[0] != LBM_PERIODIC) || (xs == g.ntx - 1 && g.face[1] != LBM_PERIODIC);
     if (yz) pull_general<ST>(f, in, x, y, z, g, inl);
     else if (xf) pull_xface<ST>(f, in, x, y, z, g, inl);
-    else if constexpr (B32 && LBM_BUF_LOADS) pull_interior_buf<ST>(f, make_rsrc(in, bytes), x, y, z, g);
     else pull_interior<ST>(f, in, x, y, z, g);
 }
 
-// Per-node choice for kernels whose lanes hold unrelated nodes (band nodes,
-// dense macros): the plain periodic pull when no source crosses a
-// non-periodic face, the face-aware one otherwise.
-template <int ST, typename R>
-__device__ __forceinline__ void pull_node(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int x, int y,
-                                          int z, const Geom &g, const Inlet<R> &inl)
-{
-    const bool free = (x > 0 || g.face[0] == LBM_PERIODIC) && (x < g.nx - 1 || g.face[1] == LBM_PERIODIC) &&
-                      (y > 0 || g.face[2] == LBM_PERIODIC) && (y < g.ny - 1 || g.face[3] == LBM_PERIODIC) &&
-                      (z > 0 || g.face[4] == LBM_PERIODIC) && (z < g.nz - 1 || g.face[5] == LBM_PERIODIC);
-    if (free) pull_interior<ST>(f, in, x, y, z, g);
-    else pull_general<ST>(f, in, x, y, z, g, inl);
-}
 
 // ---------------------------------------------------------------------------
 // collision (Eqs. 4-5) in deviation form
@@ -663,6 +609,25 @@ template <typename R> __device__ __forceinline__ Macro<R> moments01(const R (&f)
         if (CZ[i]) m.jz += CZ[i] > 0 ? v : -v;
     }
     return m;
+}
+
+// Eq. (2) moments (drho = rho - 1, j) of the streamed deviations at one node,
+// for kernels whose lanes hold unrelated nodes (band nodes, dense macros):
+// the plain periodic pull when no source crosses a non-periodic face, the
+// face-aware one otherwise.  Both are unrolled so that the 27 loads are in
+// flight together (a compact loop over the face rules waits for each load in
+// turn and measured slower).
+template <int ST, typename R>
+__device__ __forceinline__ Macro<R> node_moments(const typename Store<ST>::T *__restrict__ in, int x, int y, int z,
+                                                 const Geom &g, const Inlet<R> &inl)
+{
+    const bool free = (x > 0 || g.face[0] == LBM_PERIODIC) && (x < g.nx - 1 || g.face[1] == LBM_PERIODIC) &&
+                      (y > 0 || g.face[2] == LBM_PERIODIC) && (y < g.ny - 1 || g.face[3] == LBM_PERIODIC) &&
+                      (z > 0 || g.face[4] == LBM_PERIODIC) && (z < g.nz - 1 || g.face[5] == LBM_PERIODIC);
+    R f[3][3][3];
+    if (free) pull_interior<ST>(f, in, x, y, z, g);
+    else pull_general<ST>(f, in, x, y, z, g, inl);
+    return moments01(f);
 }
 
 }  // namespace lbm

@@ -67,10 +67,10 @@ __device__ __forceinline__ void scalar_update(const StepParams<ST> &P, int x, in
 // ---------------------------------------------------------------------------
 // fused step
 // ---------------------------------------------------------------------------
-// B32: both population copies are below 2^31 bytes, so every offset is a
-// 32-bit value and interior loads and all stores go through buffer
-// descriptors (uniform part in a scalar register, no 64-bit vector address
-// arithmetic).
+// B32: the 27 populations of one row lie within 2^31 bytes of the row's start
+// (always for the blocked layout), so the stores go through a buffer
+// descriptor based at the row: population offset in a scalar register, x
+// offset in one 32-bit vector register, no 64-bit vector address arithmetic.
 template <int ST, bool BAND, bool SCALAR, bool B32>
 __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams<ST> P)
 {
@@ -86,10 +86,9 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     const int x = xs * SEG + lane;
     const bool active = x < g.nx;
     const int xc = active ? x : g.nx - 1;
-    const uint32_t bytes = (uint32_t)(g.total * (int64_t)sizeof(T));
 
     R f[3][3][3];
-    pull_wave<ST, B32>(f, P.fin, bytes, xs, xc, y, z, g, P.inlet);
+    pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
 
     R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
     if (BAND) {
@@ -106,13 +105,12 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     collide(f, Fx, Fy, Fz, P.rt, rho, ux, uy, uz);
     if (active) {
         if constexpr (B32 && LBM_BUF_STORES) {
-            const BufRsrc rout = make_rsrc(P.fout, bytes);
-            const uint32_t ro = row_off32(g, (uint32_t)(z * g.ny + y));
+            const BufRsrc rout = make_rsrc(P.fout + row_off(g, y, z), (uint32_t)(Q * g.plane * (int64_t)sizeof(T)));
             const uint32_t xb = (uint32_t)(x * sizeof(T));
 #pragma unroll
             for (int i = 0; i < Q; ++i)
                 buf_st_nt<T>(Store<ST>::enc(f[CZ[i] + 1][CY[i] + 1][CX[i] + 1]), rout, xb,
-                             ((uint32_t)i * (uint32_t)g.plane + ro) * (uint32_t)sizeof(T));
+                             (uint32_t)i * (uint32_t)(g.plane * (int64_t)sizeof(T)));
         } else {
             const int64_t base = row_off(g, y, z) + x;
 #pragma unroll
@@ -140,9 +138,7 @@ __global__ void __launch_bounds__(256)
     const int x = (int)(cell % g.nx);
     const int64_t r = cell / g.nx;
     const int y = (int)(r % g.ny), z = (int)(r / g.ny);
-    R f[3][3][3];
-    pull_node<ST>(f, P.fin, x, y, z, g, P.inlet);
-    const Macro<R> m = moments01(f);
+    const Macro<R> m = node_moments<ST>(P.fin, x, y, z, g, P.inlet);
     const R rho = (R)1 + m.drho, inv = (R)1 / rho;
     typename StepParams<ST>::R4 v;
     v.x = rho;

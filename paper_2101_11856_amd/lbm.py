@@ -182,6 +182,13 @@ class Solver:
         except Exception:
             pass
 
+    def set_stream(self, stream):
+        """Issue this solver's further work on `stream` (a torch.cuda.Stream).
+        Tensors the binding creates or reads are produced on torch's current
+        stream: use the solver inside `torch.cuda.stream(stream)`."""
+        self.stream = stream
+        _check(_L.lbm_set_stream(self._h, C.c_void_p(stream.cuda_stream)), self._h)
+
     def set_inlet_profile(self, prof):
         """Replace the contents of the inlet profile given at construction."""
         if self._inlet is None:
