@@ -131,8 +131,10 @@ lbm_status lbm_set_solids(lbm_ctx *ctx, int64_t n, const float *xyz, const float
 
 /* Advance n time steps (Alg. 2): for each step, pull streaming with the face
  * rules (Eq. 3), rho and u (Eq. 2), then if samples are set: interpolation
- * and penalty force (Eqs. 6-7) and spreading by per-sample scattering with
- * atomic additions (Eq. 8, Sec. 4.3.2), then the central-moment collision with
+ * and penalty force (Eqs. 6-7) and spreading (Eq. 8) in a deterministic
+ * order (the samples of one base cell are summed per stencil offset, then
+ * every band node gathers its at most 8 run sums; no floating-point atomics,
+ * so repeated runs are bit-identical), then the central-moment collision with
  * force (Eqs. 4-5), stored to the other population buffer.  Async. */
 lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps);
 
@@ -162,7 +164,9 @@ lbm_status lbm_ib_force_eval(lbm_ctx *ctx, double out[3]);
 lbm_status lbm_solid_maps(lbm_ctx *ctx, uint8_t *flags, int32_t *marker_cell, int32_t *marker_perm);
 
 /* Snapshot of the state (populations and scalar) into / from device memory of
- * lbm_state_bytes() bytes, caller-owned.  Async. */
+ * lbm_state_bytes() bytes, caller-owned.  The bytes are the internal storage
+ * (population deviations in the blocked layout, in the storage type): opaque,
+ * and valid only for a context created with the same parameters.  Async. */
 lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
 lbm_status lbm_checkpoint(lbm_ctx *ctx, void *dst);
 lbm_status lbm_restore(lbm_ctx *ctx, const void *src);

@@ -8,8 +8,13 @@
 //                  penalty (Eq. 7) reversed -> dJ/dgamma_s; interpolation
 //                  transposed = scatter into the band adjoints of (rho, u0)
 //   k_adj_band     per band node: (rho, u0) = moments of f* (Eq. 2) reversed
-//   k_adj_push     per node: streaming transposed (every face rule), with the
-//                  inlet's wall-velocity term giving dJ/du_in(y, z)
+//   k_adj_gather   per node: streaming transposed for plain pulls, as a
+//                  gather (each entry written once)
+//   k_adj_faces    face-layer nodes: streaming transposed for the face rules
+//                  (atomic adds), with the inlet's wall-velocity term giving
+//                  dJ/du_in(y, z)
+//   k_adj_push     per node, all rules by scattering (adds to lambda; used by
+//                  the seeds, which accumulate)
 #include "lbm_adjoint.hpp"
 #include "lbm_ctx.hpp"
 
@@ -208,6 +213,76 @@ __global__ void __launch_bounds__(256) k_adj_push(Geom g, const R *__restrict__ 
     }
 }
 
+// Streaming transposed for a whole step, in two parts.
+// Plain part (gather, overwrites lambda): a value f_j(y) read by a plain pull
+// (source inside the domain, periodic axes wrapped) is read by node y + c_j
+// only, so lambda_j(y) = mu_j(y + c_j) when that node exists, else 0.  No
+// atomics: each entry is written once.
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_gather(Geom g, const R *__restrict__ M, R *__restrict__ lam)
+{
+    const int lane = threadIdx.x & (SEG - 1);
+    const uint32_t w = blockIdx.x * 4u + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / SEG);
+    if (w >= (uint32_t)g.W) return;
+    int xs, y, z;
+    wave_coords(w, g, xs, y, z);
+    const int x = xs * SEG + lane;
+    if (x >= g.nx) return;
+    const bool px = g.face[0] == LBM_PERIODIC, py = g.face[2] == LBM_PERIODIC, pz = g.face[4] == LBM_PERIODIC;
+    // destination coordinate along one axis (c = +1 / -1), or -1 if it lies beyond a non-periodic face
+    auto step = [](int v, int c, int n, bool periodic) {
+        const int t = v + c;
+        if (t >= 0 && t < n) return t;
+        return periodic ? (t < 0 ? n - 1 : 0) : -1;
+    };
+    const int xd[3] = {step(x, -1, g.nx, px), x, step(x, 1, g.nx, px)};
+    const int yd[3] = {step(y, -1, g.ny, py), y, step(y, 1, g.ny, py)};
+    const int zd[3] = {step(z, -1, g.nz, pz), z, step(z, 1, g.nz, pz)};
+    const int64_t base = row_off(g, y, z) + x;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const int tx = xd[CX[j] + 1], ty = yd[CY[j] + 1], tz = zd[CZ[j] + 1];
+        R v = (R)0;
+        if (tx >= 0 && ty >= 0 && tz >= 0) v = M[(int64_t)j * g.plane + row_off(g, ty, tz) + tx];
+        lam[(int64_t)j * g.plane + base] = v;
+    }
+}
+
+// Face part (adds to lambda after k_adj_gather): every pull (i, x) whose source
+// lies beyond a non-periodic face (bounce-back, inlet, outflow, free slip)
+// adds mu_i(x) to the adjoint of the population the face rule read; the inlet
+// term adds mu_i 2 w_i c_i / cs^2 to dJ/du_in.  Only face-layer nodes have such
+// pulls; one lane per face-layer node.
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_faces(Geom g, FaceSet F, const R *__restrict__ M, R *__restrict__ lam,
+                                                   double *__restrict__ g_inlet)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= F.na + F.nb) return;
+    int x, y, z;
+    face_node(k, g, F, x, y, z);
+    const bool px = !F.xf, py = !F.yf, pz = !F.zf;
+    const int64_t base = row_off(g, y, z) + x;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int sx = x - CX[i], sy = y - CY[i], sz = z - CZ[i];
+        const bool plain = (px || (sx >= 0 && sx < g.nx)) && (py || (sy >= 0 && sy < g.ny)) &&
+                           (pz || (sz >= 0 && sz < g.nz));
+        if (plain) continue;
+        const R mu = M[(int64_t)i * g.plane + base];
+        const PullSrc s = resolve(i, x, y, z, g);
+        unsafeAtomicAdd(lam + (int64_t)s.pl * g.plane + row_off(g, s.sy, s.sz) + s.sx, mu);
+        if (s.inlet && g_inlet) {
+            const double c = 6.0 * weight(i) * (double)mu;
+            const int64_t row = (int64_t)s.sz * g.ny + s.sy;
+            const int64_t nyz = (int64_t)g.ny * g.nz;
+            if (CX[i]) unsafeAtomicAdd(g_inlet + row, CX[i] * c);
+            if (CY[i]) unsafeAtomicAdd(g_inlet + nyz + row, CY[i] * c);
+            if (CZ[i]) unsafeAtomicAdd(g_inlet + 2 * nyz + row, CZ[i] * c);
+        }
+    }
+}
+
 // Seed of an objective on lbm_macros: mu_i = g_rho + g_u . (c_i - u0) / rho
 template <int ST>
 __global__ void __launch_bounds__(256) k_adj_seed_macros(Geom g, const typename Store<ST>::T *__restrict__ fin,
@@ -348,9 +423,12 @@ template <int ST> static hipError_t step_st(lbm_ctx *c, const void *state, doubl
     else hipLaunchKernelGGL((k_adj_collide<ST, false>), grid, block, 0, c->stream, P);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (c->nm > 0 && (e = adj_ib_part<R>(c, g_gain)) != hipSuccess) return e;
-    if ((e = launch_zero(c, c->lam_out, (size_t)c->g.total * c->rsize)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_adj_push<R>), grid, block, 0, c->stream, c->g, static_cast<const R *>(c->adjM),
-                       static_cast<R *>(c->lam_out), g_inlet);
+    hipLaunchKernelGGL((k_adj_gather<R>), grid, block, 0, c->stream, c->g, static_cast<const R *>(c->adjM),
+                       static_cast<R *>(c->lam_out));
+    const FaceSet F = face_set(c->g);
+    if (F.na + F.nb > 0)
+        hipLaunchKernelGGL((k_adj_faces<R>), g1(F.na + F.nb), block, 0, c->stream, c->g, F,
+                           static_cast<const R *>(c->adjM), static_cast<R *>(c->lam_out), g_inlet);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(c->lam_in, c->lam_out);
     return hipSuccess;

@@ -186,6 +186,54 @@ __host__ __device__ __forceinline__ int64_t row_off(const Geom &g, int y, int z)
     return row_off(g, (int64_t)z * g.ny + y);
 }
 
+// Face-layer nodes, enumerated densely (one lane each): part A = every node
+// of the rows on a non-periodic y or z face (y faces first: y = 0, ny-1 for
+// each z; then z = 0, nz-1 for the y not on a y face); part B = the two x-face
+// nodes (x = 0, nx-1) of every other row, when the x faces are non-periodic.
+struct FaceSet {
+    int yf, zf, xf;     // axes with non-periodic faces
+    int ry, rz;         // rows of part A on y faces / on z faces
+    int y0, ny1, z0;    // part B rows: y in [y0, y0 + ny1), z from z0
+    int64_t na, nb;     // node counts of parts A and B
+};
+__host__ __device__ inline FaceSet face_set(const Geom &g)
+{
+    FaceSet F{};
+    F.yf = g.face[2] != LBM_PERIODIC;
+    F.zf = g.face[4] != LBM_PERIODIC;
+    F.xf = g.face[0] != LBM_PERIODIC;
+    F.ry = F.yf ? 2 * g.nz : 0;
+    F.y0 = F.yf ? 1 : 0;
+    F.ny1 = g.ny - 2 * F.y0;
+    F.rz = F.zf ? 2 * F.ny1 : 0;
+    F.z0 = F.zf ? 1 : 0;
+    F.na = (int64_t)(F.ry + F.rz) * g.nx;
+    const int64_t other = (int64_t)F.ny1 * (g.nz - 2 * F.z0);
+    F.nb = F.xf ? 2 * other : 0;
+    return F;
+}
+__host__ __device__ __forceinline__ void face_node(int64_t k, const Geom &g, const FaceSet &F, int &x, int &y, int &z)
+{
+    if (k < F.na) {
+        const int r = (int)(k / g.nx);
+        x = (int)(k - (int64_t)r * g.nx);
+        if (r < F.ry) {
+            y = (r & 1) ? g.ny - 1 : 0;
+            z = r >> 1;
+        } else {
+            const int q = r - F.ry;
+            z = (q & 1) ? g.nz - 1 : 0;
+            y = F.y0 + (q >> 1);
+        }
+    } else {
+        const int64_t b = k - F.na;
+        x = (b & 1) ? g.nx - 1 : 0;
+        const int64_t r = b >> 1;
+        y = F.y0 + (int)(r % F.ny1);
+        z = F.z0 + (int)(r / F.ny1);
+    }
+}
+
 // Raw buffer access: the descriptor holds a wave-uniform 64-bit base, the
 // uniform part of an offset goes in a scalar register (soffset) and the
 // per-lane part in a 32-bit vector register, so an access costs no vector

@@ -66,6 +66,41 @@ static int check_layout(int nx, int ny, int nz, int lr)
     return bad;
 }
 
+// every node on a non-periodic face layer exactly once, nothing else
+static int check_faces(int nx, int ny, int nz, int xf, int yf, int zf)
+{
+    Geom g{};
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    const int P = LBM_PERIODIC, N = LBM_NOSLIP;
+    const int fc[6] = {xf ? LBM_INLET : P, xf ? LBM_OUTFLOW : P, yf ? N : P, yf ? N : P, zf ? N : P, zf ? N : P};
+    for (int k = 0; k < 6; ++k) g.face[k] = fc[k];
+    const FaceSet F = face_set(g);
+    std::vector<int> hit((size_t)nx * ny * nz, 0);
+    int bad = 0;
+    for (int64_t k = 0; k < F.na + F.nb; ++k) {
+        int x, y, z;
+        face_node(k, g, F, x, y, z);
+        if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) {
+            if (bad++ < 5) std::printf("faces %dx%dx%d: k=%lld out of range\n", nx, ny, nz, (long long)k);
+            continue;
+        }
+        hit[(size_t)x + (size_t)nx * (y + (size_t)ny * z)]++;
+    }
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const bool face = (xf && (x == 0 || x == nx - 1)) || (yf && (y == 0 || y == ny - 1)) ||
+                                  (zf && (z == 0 || z == nz - 1));
+                const int h = hit[(size_t)x + (size_t)nx * (y + (size_t)ny * z)];
+                if (h != (face ? 1 : 0)) {
+                    if (bad++ < 5) std::printf("faces %dx%dx%d (%d%d%d): node (%d,%d,%d) hit %d times\n", nx, ny, nz, xf, yf, zf, x, y, z, h);
+                }
+            }
+    return bad;
+}
+
 int main()
 {
     std::mt19937_64 rng(2101);
@@ -77,6 +112,10 @@ int main()
     for (auto &d : dims)
         for (int lr : {0, 1, 2, 3, 4, 31})
             if (lr == 31 || (int64_t(1) << lr) <= (int64_t)d[1] * d[2]) bad += check_layout(d[0], d[1], d[2], lr);
+    const int fd[][3] = {{7, 5, 4}, {2, 2, 2}, {2, 3, 2}, {5, 2, 3}, {64, 9, 6}, {70, 18, 15}, {3, 1, 4}};
+    for (auto &d : fd)
+        for (int m = 0; m < 8; ++m)
+            if ((!(m & 2) || d[1] >= 2) && (!(m & 4) || d[2] >= 2)) bad += check_faces(d[0], d[1], d[2], m & 1, (m >> 1) & 1, (m >> 2) & 1);
     std::printf(bad ? "FAIL %d\n" : "OK\n", bad);
     return bad != 0;
 }

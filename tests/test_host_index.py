@@ -1,7 +1,9 @@
 """Host checks of the kernels' index arithmetic: the invariant-divisor
-division used to split a work item into (segment, y, z), and the CSoA
-population offsets (every (population, row, x) maps to a distinct element
-inside one copy, also with a ragged last block).  Compiles a small host
+division used to split a work item into (segment, y, z), the CSoA population
+offsets (every (population, row, x) maps to a distinct element inside one
+copy, also with a ragged last block), and the dense enumeration of the
+face-layer nodes used by the adjoint's face kernel (every node on a
+non-periodic face layer exactly once, nothing else).  Compiles a small host
 program against the kernel header with hipcc; CPU only."""
 import os
 import shutil
