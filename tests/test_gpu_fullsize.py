@@ -167,3 +167,100 @@ def test_passive_scalar_many_steps():
     e_s = rel_l2(sc, S.get_scalar())
     say(f"  rel-L2 scalar={e_s:.3e}")
     assert e_s <= 1e-5
+
+
+def _smooth_fields(nx, ny, nz):
+    """Non-trivial smooth initial fields (float32, separable products), so that
+    the first step changes every node: rho = 1 + 1e-3 a, u = (0.05 + 0.01 b,
+    0.005 c, 0.005 d), scalar in [0, 1]."""
+    X = np.arange(nx, dtype=np.float32)
+    Y = np.arange(ny, dtype=np.float32)
+    Z = np.arange(nz, dtype=np.float32)
+    two_pi = np.float32(2 * np.pi)
+
+    def sep(fx, fy, fz):
+        return (fz[:, None, None] * fy[None, :, None]) * fx[None, None, :]
+
+    sx, cy, sz = np.sin(two_pi * 3 * X / nx), np.cos(two_pi * 2 * Y / ny), np.sin(two_pi * 5 * Z / nz)
+    cx, sy, cz = np.cos(two_pi * 4 * X / nx), np.sin(two_pi * 3 * Y / ny), np.cos(two_pi * 2 * Z / nz)
+    rho = np.float32(1) + np.float32(1e-3) * sep(sx, sy, cz)
+    u = np.empty((3, nz, ny, nx), np.float32)
+    u[0] = np.float32(0.05) + np.float32(0.01) * sep(cx, cy, sz)
+    u[1] = np.float32(0.005) * sep(sx, cy, cz)
+    u[2] = np.float32(0.005) * sep(cx, sy, sz)
+    sc = np.float32(0.5) + np.float32(0.5) * sep(sx, cy, cz)
+    return rho, u, sc
+
+
+def test_city_full_size_maps_and_sampled_nodes():
+    """City 1200x250x840 at full size (252M nodes, 3.86M samples), in the
+    launch configuration the benchmark times.  The FP64 oracle cannot step the
+    whole domain (its state is ~110 GB), so: (1) the integer maps are compared
+    bit for bit with the oracle's at full size (its maps need only the sample
+    arrays); (2) after one GPU step, nodes sampled at the band, the inlet, the
+    outflow, the ground, the top and across the periodic z seam are compared
+    with the oracle run on a 17^3 box centred on each node.  One step of the
+    method depends on a node's neighbourhood within 3 nodes (pull, the samples
+    around the node, their stencils' pulls), so a box that keeps the real faces
+    where it touches them and puts its own faces >= 5 nodes away gives the
+    node's exact result."""
+    say("city 1200x250x840 full size: maps bit-exact + one step at sampled nodes vs oracle boxes, fp32")
+    nx, ny, nz = 1200, 250, 840
+    faces = (IN, OUT, NS, FS, P, P)
+    h_sc = 50
+    xyz, ub, area, gain = synth.city_markers(synth.city_boxes())
+    n = xyz.shape[1]
+    rho, u, sc0 = _smooth_fields(nx, ny, nz)
+    s = gpu_solver(nx, ny, nz, 1e-5, faces=faces, u_in=(0.05, 0, 0), scalar=True, scalar_inlet_height=h_sc)
+    s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+    s.set_scalar(torch.from_numpy(sc0).cuda())
+    s.set_solids(xyz, ub, area, gain)
+    fl, cell, perm = (t.cpu().numpy() for t in s.solid_maps())
+
+    # (1) maps at full size against the oracle
+    S = O.OracleSim(nx, ny, nz, 1e-5, faces=faces, u_in=(0.05, 0, 0))
+    S.set_markers(xyz, ub.astype(np.float64), area.astype(np.float64), gain.astype(np.float64))
+    fl_ref, cell_ref, perm_ref = S.maps()
+    S.close()
+    assert np.array_equal(cell, cell_ref) and np.array_equal(perm, perm_ref) and np.array_equal(fl, fl_ref)
+    say(f"  maps bit-exact: {n} samples, {int((fl & 1).sum())} band nodes")
+
+    # (2) one step, sampled nodes
+    s.step(1)
+    rng = np.random.default_rng(84)
+    band = np.flatnonzero(fl & 1)
+    picks = [np.unravel_index(k, (nz, ny, nx))[::-1] for k in rng.choice(band, 8, replace=False)]
+    picks += [(0, 20, 100), (1, 60, 401), (nx - 1, 30, 7), (nx - 2, 200, 838), (500, 0, 300), (700, 1, 0),
+              (900, ny - 1, 839), (333, ny - 2, 420), (0, 0, 0), (nx - 1, ny - 1, nz - 1)]
+    picks += [tuple(int(v) for v in rng.integers((0, 0, 0), (nx, ny, nz))) for _ in range(6)]
+    idx = torch.tensor([x + nx * (y + ny * z) for x, y, z in picks], device="cuda")
+    f_gpu = s.get_populations().reshape(27, -1)[:, idx].double().cpu().numpy()
+    sc_gpu = s.get_scalar().reshape(-1)[idx].double().cpu().numpy()
+    del s
+    torch.cuda.empty_cache()
+
+    H = 8                       # box half-width: nodes at distance >= 5 from artificial faces
+    worst_f = worst_s = 0.0
+    for k, (x, y, z) in enumerate(picks):
+        x0, x1 = max(0, x - H), min(nx, x + H + 1)
+        y0, y1 = max(0, y - H), min(ny, y + H + 1)
+        zr = np.arange(z - H, z + H + 1) % nz          # periodic axis: a slice across the seam
+        bx, by, bz = x1 - x0, y1 - y0, len(zr)
+        B = O.OracleSim(bx, by, bz, 1e-5, faces=faces, u_in=(0.05, 0, 0), scalar=True)
+        # samples of the box, in box coordinates (their order is kept)
+        zoff = (xyz[2] - (z - H)) % nz
+        keep = ((xyz[0] >= x0) & (xyz[0] < x1 - 1) & (xyz[1] >= y0) & (xyz[1] < y1 - 1) & (zoff < bz - 1))
+        bxyz = np.stack([xyz[0][keep] - x0, xyz[1][keep] - y0, zoff[keep]]).astype(np.float32)
+        B.set_markers(bxyz, ub[:, keep].astype(np.float64), area[keep].astype(np.float64),
+                      gain[keep].astype(np.float64))
+        B.init_equilibrium(rho[zr][:, y0:y1, x0:x1].astype(np.float64), u[:, zr][:, :, y0:y1, x0:x1].astype(np.float64))
+        B.set_scalar(sc0[zr][:, y0:y1, x0:x1].astype(np.float64), h_sc - y0 if x0 == 0 else 0)
+        B.step(1)
+        f_ref = B.get_state()[:, H, y - y0, x - x0]
+        s_ref = B.get_scalar()[H, y - y0, x - x0]
+        B.close()
+        e_f = float(np.abs(f_gpu[:, k] - f_ref).max() / np.abs(f_ref).max())
+        e_s = abs(sc_gpu[k] - s_ref)
+        worst_f, worst_s = max(worst_f, e_f), max(worst_s, e_s)
+        assert e_f <= 1e-6 and e_s <= 1e-6, (picks[k], e_f, e_s)
+    say(f"  {len(picks)} sampled nodes: max rel err populations {worst_f:.2e}, scalar {worst_s:.2e}")
