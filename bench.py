@@ -110,12 +110,13 @@ def sphere_workload(steps, warmup):
     s.init_equilibrium(rho, u)
     xyz, ub, area, gain = synth.sphere_scene()
     s.set_solids(xyz, ub, area, gain)
+    band = int((s.solid_maps()[0] & 1).sum())
     t = timed_steps(s, steps, warmup)
     F = s.ib_force()
     out = {"workload": "flow past an immersed sphere 512x128x128, inlet/outflow, 13000 sphere + 200000 "
                        "random samples, FP32", "value": round(nx * ny * nz * steps / t / 1e6, 1),
            "unit": "MLUPS", "ms_per_step": round(1e3 * t / steps, 4), "samples": int(xyz.shape[1]),
-           "band_nodes": None, "drag_x": float(-F[0])}
+           "band_nodes": band, "drag_x": float(-F[0])}
     del s
     torch.cuda.empty_cache()
     return out
@@ -138,11 +139,12 @@ def city_workload(steps, warmup, storage="f32"):
     s.set_scalar(torch.zeros((nz, ny, nx), dtype=torch.float32, device="cuda"))
     xyz, ub, area, gain = synth.city_markers(synth.city_boxes())
     s.set_solids(xyz, ub, area, gain)
+    band = int((s.solid_maps()[0] & 1).sum())
     t = timed_steps(s, steps, warmup)
     cells = nx * ny * nz
     out = {"workload": f"city blocks 1200x250x840, {xyz.shape[1]} samples, passive scalar, {storage.upper()}",
            "value": round(cells * steps / t / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(1e3 * t / steps, 3),
-           "samples": int(xyz.shape[1]), "cells": cells,
+           "samples": int(xyz.shape[1]), "band_nodes": band, "cells": cells,
            "population_bytes": 2 * 27 * cells * (4 if storage == "f32" else 2)}
     del s
     torch.cuda.empty_cache()

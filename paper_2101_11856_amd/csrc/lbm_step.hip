@@ -1,8 +1,11 @@
 // lbm_step.hip -- the per-step kernels of liblbm (Alg. 2 of the paper):
-//   k_band   (a)+(b) on the immersed-boundary band only: pull + rho, u
-//   k_ib     (c) interpolation, penalty force, spreading by scattering
-//   k_fused  (a)+(b)+(d)+(e) for every node: pull with face rules, rho and u,
-//            band force, central-moment collision, store
+//   k_band      (a)+(b) on the immersed-boundary band only: pull + rho, u
+//   k_ib_run    (c) interpolation and penalty force per sample; per run of
+//               samples sharing a base cell, the 8 spreading sums
+//   k_ib_total  (c) FP64 total force from per-block partials, in order
+//   k_spread    (c) spreading completed: each band node gathers its run sums
+//   k_fused     (a)+(b)+(d)+(e) for every node: pull with face rules, rho and
+//               u, band force, central-moment collision, store
 #include "lbm_ctx.hpp"
 
 namespace lbm {
