@@ -40,8 +40,14 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(LIB)
+        # LBM_ORACLE_LIBRARY: a deliberately broken copy, for the mutation test
+        # of the pins (tests/test_oracle_mutants.py); never set otherwise
+        alt = os.environ.get("LBM_ORACLE_LIBRARY")
+        if alt:
+            L = C.CDLL(alt)
+        else:
+            build()
+            L = C.CDLL(LIB)
         dp, ip, fp = C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_float)
         vp = C.c_void_p
         L.orc_lattice.argtypes = [ip, dp, ip, ip]

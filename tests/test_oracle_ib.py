@@ -172,3 +172,22 @@ def test_maps_match_brute_force():
             assert v not in seen
             seen.add(v)
             prev = v
+
+
+def test_penalty_force_uses_gain_and_area():
+    """Eq. (7) with the sample's gain and Eq. (8)'s area weight, by hand: in a
+    uniform state (rho, U) the interpolation of constants is exact, so
+    G_s = gamma_s rho (u_b,s - U) and the total force is sum_s a_s G_s."""
+    nx, ny, nz = 8, 8, 8
+    rho0, U = 1.02, np.array([0.03, -0.01, 0.02])
+    S = O.OracleSim(nx, ny, nz, 0.05)
+    S.init_equilibrium(np.full((nz, ny, nx), rho0), np.broadcast_to(U[:, None, None, None], (3, nz, ny, nx)).copy())
+    xyz = np.array([[2.25, 5.5, 3.75], [3.5, 2.0, 6.25], [4.75, 4.5, 1.5]], np.float32)
+    ub = np.array([[0.01, 0.0, -0.02], [0.0, 0.03, 0.01], [0.02, 0.0, 0.0]])
+    gain = np.array([0.5, 2.0, 1.5])
+    area = np.array([0.3, 1.7, 0.9])
+    S.set_markers(xyz, ub=ub, area=area, gain=gain)
+    F, G = S.ib_force(per_marker=True)
+    G_hand = gain * rho0 * (ub - U[:, None])
+    assert np.abs(G - G_hand).max() < 1e-15
+    assert np.abs(F - G_hand @ area).max() < 1e-15

@@ -1,0 +1,89 @@
+"""Mutation test of the oracle's pins: each entry plants one plausible mistake
+in a temporary copy of the oracle source (a dropped term, a wrong sign, index
+or operand, a misplaced face rule), builds it, and runs the pin suite against
+it; every mutant must make some pin fail.  An unmutated copy built the same
+way must pass, so a broken harness cannot pass for a caught mutant.  The
+committed oracle is never modified.  CPU only (gcc)."""
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
+PINS = ["tests/test_oracle_moments.py", "tests/test_oracle_flows.py", "tests/test_oracle_ib.py"]
+SKIP_SLOW = "not taylor_green_decay_rate and not magic_odd_rates"   # 15 s of the suite; never the only catcher
+
+# name: (text in lbm_oracle.c, replacement)
+MUTANTS = {
+    # collision (Eqs. 4-5) and the readings R2-R8
+    "force_sign": ("return F[axis] * ipow(CS2, twos);", "return -F[axis] * ipow(CS2, twos);"),
+    "force_high_orders_dropped": ("if (ones != 1) return 0.0;", "if (ones != 1 || twos > 0) return 0.0;"),
+    "no_half_force_shift": ("u[a] = (j[a] + 0.5 * F[a]) / rho;", "u[a] = j[a] / rho;"),
+    "trace_at_shear_rate": ("return (k == 9) ? s_b : s_nu;", "return s_nu;"),
+    "high_rates_reversed": ("return s_high[order - 3];", "return s_high[6 - order];"),
+    "equilibrium_moment_power": ("if (e[a] == 2) v *= CS2;", "if (e[a] == 2) v = rho * CS2;"),
+    "central_matrix_transposed": ("T[k * Q + i] = v;", "T[i * Q + k] = v;"),
+    "trace_row_sign": ("C[9 * Q + k002] = 1.0;", "C[9 * Q + k002] = -1.0;"),
+    "weights_swapped": ("(CV[i][a] == 0) ? 2.0 / 3.0 : 1.0 / 6.0", "(CV[i][a] == 0) ? 1.0 / 6.0 : 2.0 / 3.0"),
+    "equilibrium_velocity_sign": ("else v *= (1.0 / 3.0 + CV[i][a] * ua + ua * ua) * 0.5;",
+                                  "else v *= (1.0 / 3.0 - CV[i][a] * ua + ua * ua) * 0.5;"),
+    # streaming and faces (Eq. 3, Alg. 1, reading R16)
+    "pull_wrong_direction": ("src[a] = p[a] - CV[i][a];", "src[a] = p[a] + CV[i][a];"),
+    "bounce_back_same_direction": ("    case F_NOSLIP:\n        return f[opposite(i) * N + lin(S, px, py, pz)];",
+                                   "    case F_NOSLIP:\n        return f[i * N + lin(S, px, py, pz)];"),
+    "inlet_missing_factor_2": ("+ 2.0 * weight(i) * cu / CS2;", "+ weight(i) * cu / CS2;"),
+    "inlet_sign": ("+ 2.0 * weight(i) * cu / CS2;", "- 2.0 * weight(i) * cu / CS2;"),
+    "inlet_profile_yz_swapped": ("if (S->inlet) return S->inlet[((int64_t)a * S->n[2] + z) * S->n[1] + y];",
+                                 "if (S->inlet) return S->inlet[((int64_t)a * S->n[2] + y) * S->n[1] + z];"),
+    "outflow_two_inward": ("q[bestaxis] += bestside ? -1 : 1;", "q[bestaxis] += bestside ? -2 : 2;"),
+    "free_slip_reflects_all": ("            if (crossed[a]) {\n                cr[a] = -cr[a];",
+                               "            if (1) {\n                cr[a] = -cr[a];"),
+    # macros and immersed boundary (Eqs. 2, 6-8; readings R10-R15)
+    "macros_no_rho_division": ("for (int a = 0; a < 3; ++a) S->u0[a * N + k] = j[a] / rho;",
+                               "for (int a = 0; a < 3; ++a) S->u0[a * N + k] = j[a];"),
+    "penalty_sign": ("S->gain[s] * rs * (S->ub[a * n + s] - us[a]);", "S->gain[s] * rs * (us[a] - S->ub[a * n + s]);"),
+    "penalty_without_gain": ("S->gain[s] * rs * (S->ub[a * n + s] - us[a]);", "rs * (S->ub[a * n + s] - us[a]);"),
+    "trilinear_weights_swapped": ("K *= d[a] ? t : 1.0 - t;", "K *= d[a] ? 1.0 - t : t;"),
+    "spreading_without_area": ("acc[a] += S->area[s] * K * S->Gs[a * n + s];", "acc[a] += K * S->Gs[a * n + s];"),
+    "gather_offset_bits_swapped": ("const int d[3] = {code & 1, (code >> 1) & 1, (code >> 2) & 1};",
+                                   "const int d[3] = {(code >> 2) & 1, (code >> 1) & 1, code & 1};"),
+    "morton_axis_order": ("<< (3 * bit + a);", "<< (3 * bit + (2 - a));"),
+    "block_order_yx": ("const uint64_t block = (uint64_t)B[0] + (uint64_t)nb[0] * ((uint64_t)B[1] + (uint64_t)nb[1] * B[2]);",
+                       "const uint64_t block = (uint64_t)B[1] + (uint64_t)nb[1] * ((uint64_t)B[0] + (uint64_t)nb[0] * B[2]);"),
+    # passive scalar (reading R21)
+    "scalar_downwind": ("if (u[a] > 0.0) v -= u[a]", "if (u[a] < 0.0) v -= u[a]"),
+    "scalar_inlet_height_off_by_one": ("y < S->scalar_inlet_height) v = 1.0;", "y <= S->scalar_inlet_height) v = 1.0;"),
+}
+
+
+def _run_pins(source: str, workdir: str, name: str) -> subprocess.CompletedProcess:
+    c = os.path.join(workdir, f"{name}.c")
+    so = os.path.join(workdir, f"{name}.so")
+    with open(c, "w") as fh:
+        fh.write(source)
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", c, "-o", so, "-lm"], check=True,
+                   capture_output=True)
+    env = dict(os.environ, LBM_ORACLE_LIBRARY=so, OMP_NUM_THREADS="2")
+    return subprocess.run([sys.executable, "-m", "pytest", *PINS, "-q", "-x", "-k", SKIP_SLOW, "-p", "no:cacheprovider"],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_every_planted_mistake_fails_a_pin():
+    src = open(SRC).read()
+    for name, (old, _) in MUTANTS.items():
+        assert src.count(old) == 1, f"mutant {name}: its source text is not found exactly once"
+    with tempfile.TemporaryDirectory() as td:
+        control = _run_pins(src, td, "control")
+        assert control.returncode == 0, "unmutated copy fails the pins:\n" + control.stdout[-2000:]
+        with cf.ThreadPoolExecutor(4) as ex:
+            futs = {name: ex.submit(_run_pins, src.replace(old, new), td, name)
+                    for name, (old, new) in MUTANTS.items()}
+            survivors = [name for name, fut in futs.items()
+                         if fut.result().returncode == 0 or fut.result().returncode == 5]
+    assert not survivors, f"mutants no pin catches: {survivors}"
