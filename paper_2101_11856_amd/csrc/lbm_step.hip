@@ -74,7 +74,14 @@ __device__ __forceinline__ void scalar_update(const StepParams<ST> &P, int x, in
 // (always for the blocked layout), so the stores go through a buffer
 // descriptor based at the row: population offset in a scalar register, x
 // offset in one 32-bit vector register, no 64-bit vector address arithmetic.
-template <int ST, bool BAND, bool SCALAR, bool B32>
+//
+// ROW: the workgroup's waves are exactly the segments of one row (segments per
+// row == waves per workgroup) and x is periodic.  Rows on no y/z face then
+// stage the 27 source rows in LDS with aligned, coalesced loads (one per
+// population and node) and read the x-shifted values back from LDS, instead
+// of 18 misaligned global loads; all waves of a workgroup share the row, so
+// the barrier is uniform.
+template <int ST, bool BAND, bool SCALAR, bool B32, bool ROW>
 __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams<ST> P)
 {
     using R = typename Store<ST>::R;
@@ -91,7 +98,31 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     const int xc = active ? x : g.nx - 1;
 
     R f[3][3][3];
-    pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
+    if constexpr (ROW) {
+        __shared__ T row[Q][SEG * WAVES_PER_BLOCK];
+        const bool yz = (y == 0 && g.face[2] != LBM_PERIODIC) || (y == g.ny - 1 && g.face[3] != LBM_PERIODIC) ||
+                        (z == 0 && g.face[4] != LBM_PERIODIC) || (z == g.nz - 1 && g.face[5] != LBM_PERIODIC);
+        if (yz) {
+            pull_general<ST>(f, P.fin, xc, y, z, g, P.inlet);
+        } else {
+            const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+            const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+            const int ysrc[3] = {yp, y, ym};
+            const int zsrc[3] = {zp, z, zm};
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    row[i][x] = P.fin[(int64_t)i * g.plane + row_off(g, ysrc[CY[i] + 1], zsrc[CZ[i] + 1]) + x];
+            }
+            __syncthreads();
+            const int xm = xc == 0 ? g.nx - 1 : xc - 1, xp = xc == g.nx - 1 ? 0 : xc + 1;
+            const int xsrc[3] = {xp, xc, xm};
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(row[i][xsrc[CX[i] + 1]]);
+        }
+    } else {
+        pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
+    }
 
     R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
     if (BAND) {
@@ -320,10 +351,11 @@ template <int ST, bool B32> static void fused_launch(lbm_ctx *c, const StepParam
 {
     const bool band = c->nm > 0, scalar = c->p.passive_scalar != 0;
     const dim3 grid(blocks_for_items(c->g.W)), block(SEG * WAVES_PER_BLOCK);
-    if (band && scalar) hipLaunchKernelGGL((k_fused<ST, true, true, B32>), grid, block, 0, c->stream, P);
-    else if (band) hipLaunchKernelGGL((k_fused<ST, true, false, B32>), grid, block, 0, c->stream, P);
-    else if (scalar) hipLaunchKernelGGL((k_fused<ST, false, true, B32>), grid, block, 0, c->stream, P);
-    else hipLaunchKernelGGL((k_fused<ST, false, false, B32>), grid, block, 0, c->stream, P);
+    if (band && scalar) hipLaunchKernelGGL((k_fused<ST, true, true, B32, false>), grid, block, 0, c->stream, P);
+    else if (band) hipLaunchKernelGGL((k_fused<ST, true, false, B32, false>), grid, block, 0, c->stream, P);
+    else if (scalar) hipLaunchKernelGGL((k_fused<ST, false, true, B32, false>), grid, block, 0, c->stream, P);
+    else if (B32 && c->row_stage) hipLaunchKernelGGL((k_fused<ST, false, false, B32, B32>), grid, block, 0, c->stream, P);
+    else hipLaunchKernelGGL((k_fused<ST, false, false, B32, false>), grid, block, 0, c->stream, P);
 }
 
 template <int ST> static hipError_t fused_st(lbm_ctx *c)
