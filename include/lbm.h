@@ -94,7 +94,15 @@ lbm_status lbm_workspace_size(const lbm_params *p, size_t *bytes);
 /* Create a context on the current HIP device.  `workspace` is device memory of
  * at least lbm_workspace_size() bytes (256-byte aligned), `hip_stream` a
  * hipStream_t (NULL = default stream).  The state is zero (f = w) until
- * lbm_init_equilibrium / lbm_set_populations / lbm_restore.  Sync. */
+ * lbm_init_equilibrium / lbm_set_populations / lbm_restore.  Sync.
+ * Storage choices read from the environment at lbm_workspace_size and
+ * lbm_create (for measurements; results are the same up to FP32 round-off):
+ * LBM_BLOCK_ROWS = rows per population block (0 = plane-major layout; default
+ * the largest power of two with at most 2048 padded nodes per block),
+ * LBM_POINTER_PATH = 1 stores through plain pointers instead of per-row buffer
+ * descriptors, LBM_ROW_STAGE = 0 / 1 disables / forces LDS row staging of the
+ * pull (default: FP32 rows that fill one workgroup with periodic x).  Keep
+ * them unchanged between the two calls. */
 lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out);
 
 lbm_status lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
