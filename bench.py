@@ -78,12 +78,13 @@ def turbulence_solver(n, storage, rho, u):
     return s
 
 
-def cpu_baseline(rho, u, n, budget_s=12.0):
-    """FP64 oracle on a 256 x 256 x 16 periodic slab of the same field."""
+def cpu_baseline(rho, u, n, budget_s=20.0):
+    """FP64 oracle on a 256 x 256 x 32 periodic slab of the same field (about
+    10-20 s of host work)."""
     import numpy as np
 
     from oracle import oracle as O
-    nz = 16
+    nz = 32
     S = O.OracleSim(n, n, nz, 1e-4)
     S.init_equilibrium(rho[:nz].astype(np.float64), u[:, :nz].astype(np.float64))
     steps, t0 = 0, time.perf_counter()
