@@ -100,11 +100,27 @@ def _check(status: int, ctx=None):
 
 
 def _ptr(t: torch.Tensor | None):
+    """Device pointer of a contiguous GPU tensor (the library dereferences it
+    in kernels: a host tensor here would be a GPU memory fault, so it is
+    refused)."""
     if t is None:
         return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
     return C.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor | None, nbytes: int, what: str, dtype=None):
+    """Refuse a caller buffer that is too small (or of the wrong dtype) before
+    the library writes or reads past its end."""
+    if t is None:
+        return
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{what} too small: {t.numel() * t.element_size()} bytes, need {nbytes}")
 
 
 def make_params(nx, ny, nz, nu, faces=(PERIODIC,) * 6, u_in=(0.0, 0.0, 0.0), body=(0.0, 0.0, 0.0),
@@ -276,13 +292,18 @@ class Solver:
     def checkpoint(self, dst: torch.Tensor | None = None) -> torch.Tensor:
         if dst is None:
             dst = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        _need(dst, self.state_bytes(), "snapshot buffer")
         _check(_L.lbm_checkpoint(self._h, _ptr(dst)), self._h)
         return dst
 
     def restore(self, src: torch.Tensor):
-        if src.numel() * src.element_size() < self.state_bytes():
-            raise LbmError(1, "snapshot too small")
+        _need(src, self.state_bytes(), "snapshot")
         _check(_L.lbm_restore(self._h, _ptr(src)), self._h)
+
+    def _grads(self, g_inlet, g_gain):
+        nz, ny, _ = self.shape
+        _need(g_inlet, 3 * nz * ny * 8, "g_inlet ([3, nz, ny])", torch.float64)
+        _need(g_gain, self.n_markers * 8, "g_gain ([n samples])", torch.float64)
 
 
     # ------------------------------------------------------------------
@@ -296,8 +317,7 @@ class Solver:
         sb = self.state_bytes()
         if tape is None:
             tape = torch.empty((max(n, 1), sb), dtype=torch.uint8, device=self.device)
-        if tape.numel() < n * sb:
-            raise LbmError(1, "tape too small")
+        _need(tape, n * sb, "tape")
         _check(_L.lbm_record_tape(self._h, int(n), _ptr(tape)), self._h)
         return tape
 
@@ -317,13 +337,17 @@ class Solver:
     def adjoint_seed_macros(self, g_rho=None, g_u=None, g_inlet=None):
         gr = None if g_rho is None else self._real(g_rho, self.shape)
         gu = None if g_u is None else self._real(g_u, (3,) + self.shape)
+        self._grads(g_inlet, None)
         _check(_L.lbm_adjoint_seed_macros(self._h, _ptr(gr), _ptr(gu), _ptr(g_inlet)), self._h)
 
     def adjoint_seed_force(self, g_force, g_inlet=None, g_gain=None):
         gf = (C.c_double * 3)(*[float(v) for v in g_force])
+        self._grads(g_inlet, g_gain)
         _check(_L.lbm_adjoint_seed_force(self._h, gf, _ptr(g_inlet), _ptr(g_gain)), self._h)
 
     def adjoint_step(self, n: int, tape: torch.Tensor, g_inlet=None, g_gain=None):
+        _need(tape, int(n) * self.state_bytes(), "tape")
+        self._grads(g_inlet, g_gain)
         _check(_L.lbm_adjoint_step(self._h, int(n), _ptr(tape), _ptr(g_inlet), _ptr(g_gain)), self._h)
 
     def adjoint_get(self) -> torch.Tensor:

@@ -272,3 +272,32 @@ def test_empty_and_single_cell_cases():
     r, u = s.macros()
     assert abs(float(r.item()) - 1.0) < 1e-7 and float(u.abs().max()) < 1e-7
     s.step(0)
+
+
+def test_binding_refuses_unsafe_buffers():
+    """Host tensors, too-small snapshots and tapes, and gradient arrays of the
+    wrong size or dtype are refused by the binding before the library would
+    touch them in a kernel."""
+    nx, ny, nz = 12, 8, 6
+    s = gpu_solver(nx, ny, nz, 0.05, faces=(IN, OUT, NS, NS, P, P), inlet_profile=_inlet(ny, nz))
+    xyz, ub, area, gain = _ib_scene(40, 18, 16, 3)
+    keep = (xyz[0] < nx - 1) & (xyz[1] < ny - 1) & (xyz[2] < nz)
+    s.set_solids(xyz[:, keep], ub[:, keep], area[keep], gain[keep])
+    assert s.n_markers > 1
+    sb = s.state_bytes()
+    with pytest.raises(ValueError):
+        s.checkpoint(torch.empty(sb - 1, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError):
+        s.restore(torch.empty(sb, dtype=torch.uint8))                        # host memory
+    s.adjoint_init()
+    tape = s.record_tape(2)
+    with pytest.raises(ValueError):
+        s.adjoint_step(3, tape)                                                # the tape holds 2 states
+    with pytest.raises(ValueError):
+        s.adjoint_step(2, tape, torch.zeros((3, nz, ny), device="cuda"))       # float32 g_inlet
+    with pytest.raises(ValueError):
+        s.adjoint_step(2, tape, None, torch.zeros(1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        s.adjoint_seed_force((1.0, 0.0, 0.0), torch.zeros((3, nz, ny), dtype=torch.float64))   # host memory
+    s.adjoint_step(2, tape, s.new_grad_inlet(), s.new_grad_gain())             # the valid call still works
+    torch.cuda.synchronize()
