@@ -21,7 +21,7 @@
  *                     "gathering" form of Sec. 4.3.1 / Table 1)
  *   Alg. 1            bounce-back at a solid (domain) face
  *   Alg. 2            step order: stream, macros + force reset, IB, collide,
- *                     domain faces
+ *                     domain faces; total force and torque of the samples
  *   Sec. 4.2.2        solid-sample ordering: l^3 blocks in x-y-z order, Z-order
  *                     (Morton) inside a block
  *
@@ -849,6 +849,24 @@ void orc_ib_force(orc_sim *S, double *out, double *gs)
         out[a] = t;
     }
     if (gs) memcpy(gs, S->Gs, sizeof(double) * 3 * n);
+}
+
+/* Total torque, Alg. 2 (c): sum_s (x_s - o) x (a_s g_s) about the point o,
+ * of the penalty forces last computed (by the last step, or by orc_ib_force
+ * if that was called after it).  x_s is the stored FP32 position; the lever
+ * arm and the sum are FP64, in ascending sample index. */
+void orc_last_torque(const orc_sim *S, const double o[3], double *out)
+{
+    const int64_t n = S->nm;
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int64_t s = 0; s < n; ++s) {
+        const double r[3] = {(double)S->mx[s] - o[0], (double)S->mx[n + s] - o[1], (double)S->mx[2 * n + s] - o[2]};
+        const double F[3] = {S->area[s] * S->Gs[s], S->area[s] * S->Gs[n + s], S->area[s] * S->Gs[2 * n + s]};
+        t[0] += r[1] * F[2] - r[2] * F[1];
+        t[1] += r[2] * F[0] - r[0] * F[2];
+        t[2] += r[0] * F[1] - r[1] * F[0];
+    }
+    memcpy(out, t, sizeof(t));
 }
 
 /* Spread field g of the most recent step (for tests). */

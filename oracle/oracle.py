@@ -77,6 +77,7 @@ def lib():
         L.orc_macros.argtypes = [vp, dp, dp]
         L.orc_last_force.argtypes = [vp, dp]
         L.orc_ib_force.argtypes = [vp, dp, dp]
+        L.orc_last_torque.argtypes = [vp, dp, dp]
         L.orc_get_force_field.argtypes = [vp, dp]
         L.orc_conserved.argtypes = [vp, dp]
         L.orc_marker_key.argtypes = [vp, fp]
@@ -157,6 +158,35 @@ def collide(fs, F=(0.0, 0.0, 0.0), s_nu=1.0, s_b=1.0, s_high=(1.0, 1.0, 1.0, 1.0
     if rc != 0:
         raise np.linalg.LinAlgError("singular moment matrix")
     return out
+
+
+def rigid_pose(X, ub, R, o, v, w):
+    """Sample update of Alg. 2 (c) for a rigid body in prescribed motion.
+
+    The paper moves its solids (rotating torus, moving airplane) without giving
+    a kinematics rule; the reading taken here is rigid motion.  Body samples
+    X_s [3, n] with body-frame boundary velocity ub_s [3, n] are placed at
+    x_s = o + R X_s and move with u_b = R ub_s + v + w x (x_s - o).
+
+    x_s is formed in FP64 as o_a + ((R_a0 X + R_a1 Y) + R_a2 Z), one rounding
+    per operation, then rounded to FP32 (the precision in which the base cell
+    floor(x_s) is taken); the lever arm x_s - o uses that FP32 position.
+    Returns (xyz float32 [3, n], ub float64 [3, n]).
+    """
+    X = np.asarray(X, dtype=np.float64).reshape(3, -1)
+    ub = np.zeros_like(X) if ub is None else np.asarray(ub, dtype=np.float64).reshape(3, -1)
+    R = np.asarray(R, dtype=np.float64).reshape(3, 3)
+    o, v, w = (np.asarray(a, dtype=np.float64).reshape(3) for a in (o, v, w))
+    xyz = np.empty(X.shape, dtype=np.float32)
+    for a in range(3):
+        xyz[a] = (o[a] + ((R[a, 0] * X[0] + R[a, 1] * X[1]) + R[a, 2] * X[2])).astype(np.float32)
+    r = xyz.astype(np.float64) - o[:, None]
+    rot_ub = R @ ub
+    ub_w = np.empty_like(X)
+    ub_w[0] = rot_ub[0] + v[0] + (w[1] * r[2] - w[2] * r[1])
+    ub_w[1] = rot_ub[1] + v[1] + (w[2] * r[0] - w[0] * r[2])
+    ub_w[2] = rot_ub[2] + v[2] + (w[0] * r[1] - w[1] * r[0])
+    return xyz, ub_w
 
 
 def num_threads() -> int:
@@ -254,6 +284,12 @@ class OracleSim:
         gs = np.zeros((3, max(self.n_markers, 1)))
         lib().orc_ib_force(self._h, _p(out, C.c_double), _p(gs, C.c_double) if per_marker else None)
         return (out, gs[:, : self.n_markers]) if per_marker else out
+
+    def last_torque(self, origin=(0.0, 0.0, 0.0)):
+        """Torque sum_s (x_s - o) x (a_s g_s) of the penalty forces last computed (Alg. 2 (c))."""
+        out = np.zeros(3)
+        lib().orc_last_torque(self._h, _p(_d(origin), C.c_double), _p(out, C.c_double))
+        return out
 
     def force_field(self):
         g = np.zeros((3,) + self.shape)

@@ -15,7 +15,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
-PINS = ["tests/test_oracle_moments.py", "tests/test_oracle_flows.py", "tests/test_oracle_ib.py"]
+PINS = ["tests/test_oracle_moments.py", "tests/test_oracle_flows.py", "tests/test_oracle_ib.py",
+        "tests/test_oracle_motion.py"]
 SKIP_SLOW = "not taylor_green_decay_rate and not magic_odd_rates"   # 15 s of the suite; never the only catcher
 
 # name: (text in lbm_oracle.c, replacement)
@@ -55,6 +56,13 @@ MUTANTS = {
     "morton_axis_order": ("<< (3 * bit + a);", "<< (3 * bit + (2 - a));"),
     "block_order_yx": ("const uint64_t block = (uint64_t)B[0] + (uint64_t)nb[0] * ((uint64_t)B[1] + (uint64_t)nb[1] * B[2]);",
                        "const uint64_t block = (uint64_t)B[1] + (uint64_t)nb[1] * ((uint64_t)B[0] + (uint64_t)nb[0] * B[2]);"),
+    # total torque of the samples (Alg. 2 (c))
+    "torque_z_sign": ("t[2] += r[0] * F[1] - r[1] * F[0];", "t[2] += r[1] * F[0] - r[0] * F[1];"),
+    "torque_x_sign": ("t[0] += r[1] * F[2] - r[2] * F[1];", "t[0] += r[2] * F[1] - r[1] * F[2];"),
+    "torque_without_area": ("const double F[3] = {S->area[s] * S->Gs[s], S->area[s] * S->Gs[n + s], S->area[s] * S->Gs[2 * n + s]};",
+                            "const double F[3] = {S->Gs[s], S->Gs[n + s], S->Gs[2 * n + s]};"),
+    "torque_lever_reversed": ("const double r[3] = {(double)S->mx[s] - o[0], (double)S->mx[n + s] - o[1], (double)S->mx[2 * n + s] - o[2]};",
+                              "const double r[3] = {o[0] - (double)S->mx[s], o[1] - (double)S->mx[n + s], o[2] - (double)S->mx[2 * n + s]};"),
     # passive scalar (reading R21)
     "scalar_downwind": ("if (u[a] > 0.0) v -= u[a]", "if (u[a] < 0.0) v -= u[a]"),
     "scalar_inlet_height_off_by_one": ("y < S->scalar_inlet_height) v = 1.0;", "y <= S->scalar_inlet_height) v = 1.0;"),
