@@ -133,9 +133,38 @@ lbm_status lbm_solids_ws_size(const lbm_ctx *ctx, int64_t n, size_t *bytes);
  * are sorted (Sec. 4.2.2: l^3 blocks, l = 4, in x-y-z order, Morton order of
  * the position inside a block, original index on ties) and copied into
  * marker_ws (device, caller-owned, lbm_solids_ws_size bytes), so the inputs
- * may be freed afterwards.  n = 0 removes all samples.  Sync. */
+ * may be freed afterwards; a body copy in input order stays there for
+ * lbm_set_pose.  n = 0 removes all samples.  Sync. */
 lbm_status lbm_set_solids(lbm_ctx *ctx, int64_t n, const float *xyz, const float *ub, const float *area,
                           const float *gain, void *marker_ws, size_t marker_ws_bytes);
+
+/* Rigid motion of the samples: the per-step sample update of Alg. 2 (c) for a
+ * solid in prescribed motion (the paper's rotating torus and moving airplane;
+ * it gives no kinematics rule, so the reading is rigid motion).  The samples
+ * of the last lbm_set_solids are body coordinates X_s with body-frame boundary
+ * velocity ub_s; this call places them at
+ *     x_s = o + R X_s,       u_b = R ub_s + v + w x (x_s - o),
+ * R a row-major 3x3 matrix (host), o the body origin, v its velocity and w the
+ * angular velocity (host double[3] each, lattice units), then re-sorts the
+ * samples and rebuilds the force band as lbm_set_solids does.  x_s is formed
+ * in FP64 as o_a + ((R_a0 X + R_a1 Y) + R_a2 Z), one rounding per operation,
+ * and rounded to FP32, so the base cells and maps are reproducible; the
+ * identity pose (R = I, o = v = w = 0) reproduces lbm_set_solids exactly.
+ * o becomes the reference point of lbm_ib_torque.  If a placed sample leaves
+ * the domain (same rule as lbm_set_solids) the call returns LBM_E_INVAL and
+ * the previous pose stays in force.  Call it before each lbm_step(1) to move
+ * the solid every step.  Any adjoint workspace must be bound again
+ * (lbm_adjoint_init) afterwards.  Sync. */
+lbm_status lbm_set_pose(lbm_ctx *ctx, const double R[9], const double o[3], const double v[3], const double w[3]);
+
+/* lbm_set_solids for a moving solid: X (device float[3][n]) are body
+ * coordinates, which need not lie in the domain; the samples are stored and
+ * placed at the pose (R, o, v, w) as lbm_set_pose does.  ub, area, gain,
+ * marker_ws as for lbm_set_solids.  If a placed sample is outside the domain
+ * it returns LBM_E_INVAL and the context has no samples.  Sync. */
+lbm_status lbm_set_body(lbm_ctx *ctx, int64_t n, const float *X, const float *ub, const float *area,
+                        const float *gain, void *marker_ws, size_t marker_ws_bytes, const double R[9],
+                        const double o[3], const double v[3], const double w[3]);
 
 /* Advance n time steps (Alg. 2): for each step, pull streaming with the face
  * rules (Eq. 3), rho and u (Eq. 2), then if samples are set: interpolation
@@ -160,6 +189,12 @@ lbm_status lbm_conserved(lbm_ctx *ctx, double out[4]);
  * (force on the fluid; drag on the solid is its negative).  Sync. */
 lbm_status lbm_ib_force(lbm_ctx *ctx, double out[3]);
 
+/* FP64 total torque sum_s (x_s - o) x (a_s g_s) of the penalty forces applied
+ * in the last step (Alg. 2 (c)), about the origin o of the current pose (the
+ * coordinate origin after lbm_set_solids); the torque on the solid is its
+ * negative.  Sync. */
+lbm_status lbm_ib_torque(lbm_ctx *ctx, double out[3]);
+
 /* FP64 total penalty force that the next step would apply, evaluated from the
  * current state without changing it.  Sync. */
 lbm_status lbm_ib_force_eval(lbm_ctx *ctx, double out[3]);
@@ -180,7 +215,7 @@ lbm_status lbm_checkpoint(lbm_ctx *ctx, void *dst);
 lbm_status lbm_restore(lbm_ctx *ctx, const void *src);
 
 /* Replace the penalty gains gamma_s of the current samples (device float[n],
- * input order) without re-sorting.  Async. */
+ * input order) without re-sorting; later poses keep them.  Async. */
 lbm_status lbm_set_gains(lbm_ctx *ctx, const float *gain);
 
 /* ---- adjoint (reverse mode of lbm_step) ----------------------------------
@@ -195,7 +230,7 @@ lbm_status lbm_set_gains(lbm_ctx *ctx, const float *gain);
 lbm_status lbm_adjoint_ws_size(const lbm_ctx *ctx, size_t *bytes);
 
 /* Bind the adjoint workspace (device, 256-byte aligned) and set lambda = 0.
- * Must be called again after lbm_set_solids.  Async. */
+ * Must be called again after lbm_set_solids or lbm_set_pose.  Async. */
 lbm_status lbm_adjoint_init(lbm_ctx *ctx, void *adj_ws, size_t bytes);
 
 /* lambda += (d(rho, u0)/df)^T (g_rho, g_u) for the lbm_macros outputs of the

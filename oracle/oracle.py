@@ -170,7 +170,8 @@ def rigid_pose(X, ub, R, o, v, w):
 
     x_s is formed in FP64 as o_a + ((R_a0 X + R_a1 Y) + R_a2 Z), one rounding
     per operation, then rounded to FP32 (the precision in which the base cell
-    floor(x_s) is taken); the lever arm x_s - o uses that FP32 position.
+    floor(x_s) is taken); the lever arm x_s - o uses that FP32 position, and
+    (R ub)_a is summed in the same order.
     Returns (xyz float32 [3, n], ub float64 [3, n]).
     """
     X = np.asarray(X, dtype=np.float64).reshape(3, -1)
@@ -181,7 +182,7 @@ def rigid_pose(X, ub, R, o, v, w):
     for a in range(3):
         xyz[a] = (o[a] + ((R[a, 0] * X[0] + R[a, 1] * X[1]) + R[a, 2] * X[2])).astype(np.float32)
     r = xyz.astype(np.float64) - o[:, None]
-    rot_ub = R @ ub
+    rot_ub = np.array([(R[a, 0] * ub[0] + R[a, 1] * ub[1]) + R[a, 2] * ub[2] for a in range(3)])
     ub_w = np.empty_like(X)
     ub_w[0] = rot_ub[0] + v[0] + (w[1] * r[2] - w[2] * r[1])
     ub_w[1] = rot_ub[1] + v[1] + (w[2] * r[0] - w[0] * r[2])

@@ -323,22 +323,36 @@ lbm_status lbm_solids_ws_size(const lbm_ctx *c, int64_t n, size_t *bytes)
     return LBM_OK;
 }
 
-lbm_status lbm_set_solids(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area,
-                          const float *gain, void *marker_ws, size_t marker_ws_bytes)
+static bool finite_pose(const double R[9], const double o[3], const double v[3], const double w[3])
 {
-    CHECK_CTX(c);
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(R[k])) return false;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(o[a]) || !std::isfinite(v[a]) || !std::isfinite(w[a])) return false;
+    return true;
+}
+
+// Shared by lbm_set_solids (R == NULL: the samples are placed as given) and
+// lbm_set_body (the samples are body coordinates, placed at the pose).
+static lbm_status set_samples(lbm_ctx *c, const char *who, int64_t n, const float *xyz, const float *ub,
+                              const float *area, const float *gain, void *marker_ws, size_t marker_ws_bytes,
+                              const double *R, const double *o, const double *v, const double *w)
+{
     if (n < 0 || n >= (1ll << 31)) return fail(c, LBM_E_INVAL, "sample count out of range");
+    c->pose_o[0] = c->pose_o[1] = c->pose_o[2] = 0.0;
     if (n == 0) {
         c->nm = 0;
         c->nband = 0;
+        HIP_TRY(c, launch_zero(c, c->ftot, 6 * sizeof(double)), who);
         return LBM_OK;
     }
     if (!xyz) return fail(c, LBM_E_INVAL, "xyz is NULL");
+    if (R && !finite_pose(R, o, v, w)) return fail(c, LBM_E_INVAL, "R, o, v and w must be finite");
     if (!marker_ws || reinterpret_cast<uintptr_t>(marker_ws) % ALIGN)
         return fail(c, LBM_E_INVAL, "marker_ws must be non-NULL and 256-byte aligned");
     SolidsLayout L;
     hipError_t e = solids_layout(c, n, &L);
-    if (e != hipSuccess) return hip_fail(c, e, "lbm_set_solids");
+    if (e != hipSuccess) return hip_fail(c, e, who);
     if (marker_ws_bytes < L.total)
         return fail(c, LBM_E_NOMEM, "marker workspace too small: need " + std::to_string(L.total) + " bytes");
     c->nm = 0;
@@ -346,14 +360,61 @@ lbm_status lbm_set_solids(lbm_ctx *c, int64_t n, const float *xyz, const float *
     c->mws = static_cast<char *>(marker_ws);
     c->mws_bytes = marker_ws_bytes;
     int bad = 0;
-    e = solids_setup(c, n, xyz, ub, area, gain, &bad);
-    if (e != hipSuccess) return hip_fail(c, e, "lbm_set_solids");
+    e = solids_store_body(c, n, xyz, ub, area, gain);
+    if (e == hipSuccess) {
+        if (R) {
+            c->nm = n;  // solids_pose places the c->nm body samples
+            e = solids_pose(c, R, o, v, w, &bad);
+            if (e != hipSuccess || bad) c->nm = 0;
+        } else {
+            e = solids_setup(c, n, c->b_xyz, c->b_ub, c->b_area, c->b_gain, &bad);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(c, e, who);
     if (bad) {
         return fail(c, LBM_E_INVAL,
-                    std::to_string(bad) +
+                    std::to_string(bad) + (R ? " placed" : "") +
                         " sample(s) outside the domain (need [0,n) on periodic axes, [0,n-1) on bounded axes)");
     }
     c->nm = n;
+    if (R)
+        for (int a = 0; a < 3; ++a) c->pose_o[a] = o[a];
+    return LBM_OK;
+}
+
+lbm_status lbm_set_solids(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area,
+                          const float *gain, void *marker_ws, size_t marker_ws_bytes)
+{
+    CHECK_CTX(c);
+    return set_samples(c, "lbm_set_solids", n, xyz, ub, area, gain, marker_ws, marker_ws_bytes, nullptr, nullptr,
+                       nullptr, nullptr);
+}
+
+lbm_status lbm_set_body(lbm_ctx *c, int64_t n, const float *X, const float *ub, const float *area, const float *gain,
+                        void *marker_ws, size_t marker_ws_bytes, const double R[9], const double o[3],
+                        const double v[3], const double w[3])
+{
+    CHECK_CTX(c);
+    if (!R || !o || !v || !w) return fail(c, LBM_E_INVAL, "R, o, v and w must be non-NULL");
+    return set_samples(c, "lbm_set_body", n, X, ub, area, gain, marker_ws, marker_ws_bytes, R, o, v, w);
+}
+
+lbm_status lbm_set_pose(lbm_ctx *c, const double R[9], const double o[3], const double v[3], const double w[3])
+{
+    CHECK_CTX(c);
+    if (!R || !o || !v || !w) return fail(c, LBM_E_INVAL, "R, o, v and w must be non-NULL");
+    if (!finite_pose(R, o, v, w)) return fail(c, LBM_E_INVAL, "R, o, v and w must be finite");
+    if (c->nm == 0) return fail(c, LBM_E_STATE, "no solid samples (lbm_set_solids)");
+    int bad = 0;
+    const hipError_t e = solids_pose(c, R, o, v, w, &bad);
+    if (e != hipSuccess) return hip_fail(c, e, "lbm_set_pose");
+    if (bad) {
+        return fail(c, LBM_E_INVAL,
+                    std::to_string(bad) +
+                        " placed sample(s) outside the domain (need [0,n) on periodic axes, [0,n-1) on bounded "
+                        "axes); the previous pose stays");
+    }
+    for (int a = 0; a < 3; ++a) c->pose_o[a] = o[a];
     return LBM_OK;
 }
 
@@ -397,6 +458,15 @@ lbm_status lbm_ib_force(lbm_ctx *c, double out[3])
     if (!out) return fail(c, LBM_E_INVAL, "out is NULL");
     HIP_TRY(c, hipMemcpyAsync(out, c->ftot, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "lbm_ib_force");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "lbm_ib_force");
+    return LBM_OK;
+}
+
+lbm_status lbm_ib_torque(lbm_ctx *c, double out[3])
+{
+    CHECK_CTX(c);
+    if (!out) return fail(c, LBM_E_INVAL, "out is NULL");
+    HIP_TRY(c, hipMemcpyAsync(out, c->ftot + 3, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "lbm_ib_torque");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "lbm_ib_torque");
     return LBM_OK;
 }
 

@@ -252,6 +252,53 @@ __global__ void k_mk_gather(int64_t n, const int32_t *__restrict__ perm, const f
     gain_s[k] = gain ? gain[s] : 1.0f;
 }
 
+// Body copy of the caller's samples (input order); NULL ub / area / gain take
+// their defaults 0 / 1 / 1.
+__global__ void k_body_store(int64_t n, const float *__restrict__ xyz, const float *__restrict__ ub,
+                             const float *__restrict__ area, const float *__restrict__ gain, float *__restrict__ bx,
+                             float *__restrict__ bu, float *__restrict__ ba, float *__restrict__ bg)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bx[a * n + s] = xyz[a * n + s];
+        bu[a * n + s] = ub ? ub[a * n + s] : 0.0f;
+    }
+    ba[s] = area ? area[s] : 1.0f;
+    bg[s] = gain ? gain[s] : 1.0f;
+}
+
+struct Pose {
+    double R[9], o[3], v[3], w[3];  // R row-major
+};
+
+// Rigid placement (the sample update of Alg. 2 (c)): x = o + R X in FP64 with
+// one rounding per operation, in the order o_a + ((R_a0 X + R_a1 Y) + R_a2 Z),
+// then rounded to FP32, so the base cells do not depend on the compiler's
+// choice of fused operations; u_b = R ub + v + w x (x - o) with the FP32 x.
+__global__ void k_pose(int64_t n, const Pose P, const float *__restrict__ bx, const float *__restrict__ bu,
+                       float *__restrict__ wx, float *__restrict__ wu)
+{
+#pragma clang fp contract(off)
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double X[3] = {(double)bx[s], (double)bx[n + s], (double)bx[2 * n + s]};
+    const double U[3] = {(double)bu[s], (double)bu[n + s], (double)bu[2 * n + s]};
+    double r[3], ru[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double p = P.o[a] + ((P.R[3 * a] * X[0] + P.R[3 * a + 1] * X[1]) + P.R[3 * a + 2] * X[2]);
+        const float pf = (float)p;
+        wx[a * n + s] = pf;
+        r[a] = (double)pf - P.o[a];
+        ru[a] = (P.R[3 * a] * U[0] + P.R[3 * a + 1] * U[1]) + P.R[3 * a + 2] * U[2];
+    }
+    wu[s] = (float)(ru[0] + P.v[0] + (P.w[1] * r[2] - P.w[2] * r[1]));
+    wu[n + s] = (float)(ru[1] + P.v[1] + (P.w[2] * r[0] - P.w[0] * r[2]));
+    wu[2 * n + s] = (float)(ru[2] + P.v[2] + (P.w[0] * r[1] - P.w[1] * r[0]));
+}
+
 __device__ __forceinline__ void stencil_node(const MarkerGeom &mg, const float *pos, int64_t n, int64_t k, int d, int &x,
                                              int &y, int &z)
 {
@@ -268,10 +315,17 @@ __device__ __forceinline__ void stencil_node(const MarkerGeom &mg, const float *
     z = c[2];
 }
 
+// Marks the 2x2x2 stencil nodes of every sample in the tile bit masks.  The
+// samples are sorted, so those of one base cell are adjacent: only the first
+// of them marks (the others would set the same 8 bits), which keeps the
+// atomics per tile word down to a few.
 __global__ void k_mk_mark(MarkerGeom mg, int64_t n, const float *__restrict__ pos, unsigned long long *__restrict__ mask)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
+    if (k > 0 && floorf(pos[k]) == floorf(pos[k - 1]) && floorf(pos[n + k]) == floorf(pos[n + k - 1]) &&
+        floorf(pos[2 * n + k]) == floorf(pos[2 * n + k - 1]))
+        return;
     for (int d = 0; d < 8; ++d) {
         int x, y, z;
         stencil_node(mg, pos, n, k, d, x, y, z);
@@ -342,10 +396,31 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
 
 // band node t = base(run r) + d is fed by run r through offset d (one base
 // per target and offset, so no two runs write the same entry)
-__global__ void k_band_src(int64_t nruns, int64_t n, int64_t nband, const int32_t *__restrict__ run_start,
+// counts[0] = band nodes, counts[1] = runs: found on the device so that the
+// set-up reads both back with one copy at its end
+__global__ void k_counts(int64_t W, const int32_t *__restrict__ tile_start, const int32_t *__restrict__ tile_cnt,
+                         int64_t n, const int32_t *__restrict__ run_id, const int32_t *__restrict__ head,
+                         int32_t *__restrict__ counts)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counts[0] = tile_start[W - 1] + tile_cnt[W - 1];
+        counts[1] = run_id[n - 1] + head[n - 1];
+    }
+}
+
+// band_src = -1 over its first 8 * counts[0] entries (grid-stride)
+__global__ void k_clear_band_src(int32_t *__restrict__ band_src, const int32_t *__restrict__ counts)
+{
+    const int64_t total = 8 * (int64_t)counts[0];
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x)
+        band_src[k] = -1;
+}
+
+__global__ void k_band_src(int64_t n, const int32_t *__restrict__ counts, const int32_t *__restrict__ run_start,
                            const int32_t *__restrict__ slot, int32_t *__restrict__ band_src)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nband = counts[0], nruns = counts[1];
     if (r >= nruns) return;
     const int64_t k0 = run_start[r];
     for (int d = 0; d < 8; ++d) band_src[(int64_t)d * nband + slot[(int64_t)d * n + k0]] = (int32_t)r;
@@ -474,6 +549,18 @@ static MarkerGeom marker_geom(const lbm_ctx *c)
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Sample sort: hipcub's stable radix sort, which at these sizes (below 2^20
+// items) runs as a block sort plus merge passes.  Forcing its onesweep radix
+// passes instead was measured slower on MI355X for 273k 8-byte keys (about
+// 165 us against 120 us per sort).
+static hipError_t sort_samples(void *tmp, size_t &tmp_bytes, const unsigned long long *keys_in,
+                               unsigned long long *keys_out, const int32_t *idx_in, int32_t *idx_out, int64_t n,
+                               int bits, hipStream_t st)
+{
+    return hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys_in, keys_out, idx_in, idx_out, (int)n, 0, bits,
+                                              st);
+}
+
 static int key_bits(const lbm_ctx *c)
 {
     const int64_t nb = (int64_t)((c->g.nx + ELL - 1) / ELL) * ((c->g.ny + ELL - 1) / ELL) * ((c->g.nz + ELL - 1) / ELL);
@@ -504,9 +591,8 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
     L->keys_out = take(un * 8);
     L->idx_in = take(un * 4);
     size_t sort_bytes = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (unsigned long long *)nullptr,
-                                                      (unsigned long long *)nullptr, (int32_t *)nullptr,
-                                                      (int32_t *)nullptr, (int)un, 0, key_bits(c));
+    hipError_t e = sort_samples(nullptr, sort_bytes, nullptr, nullptr, nullptr, nullptr, (int64_t)un, key_bits(c),
+                                nullptr);
     if (e != hipSuccess) return e;
     L->sort_tmp_bytes = sort_bytes;
     L->sort_tmp = take(sort_bytes);
@@ -522,12 +608,19 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
     L->band_cell = take(nbmax * 4);
     L->band_ru = take(nbmax * 4 * c->rsize);
     L->band_force = take(nbmax * 4 * c->rsize);
-    L->ib_part = take(((un + 255) / 256) * 4 * 8);
+    L->ib_part = take(((un + 255) / 256) * 8 * 8);
     L->run_head = take(un * 4);
     L->run_id = take(un * 4);
     L->run_start = take((un + 1) * 4);
     L->run_sum = take(8 * un * 4 * c->rsize);
     L->band_src = take(8 * nbmax * 4);
+    L->cell2 = take(un * 4);
+    L->body_xyz = take(3 * un * 4);
+    L->body_ub = take(3 * un * 4);
+    L->body_area = take(un * 4);
+    L->body_gain = take(un * 4);
+    L->world_xyz = take(3 * un * 4);
+    L->world_ub = take(3 * un * 4);
     L->misc = take(256);
     L->total = o;
     return hipSuccess;
@@ -545,9 +638,9 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
     auto *keys_out = reinterpret_cast<unsigned long long *>(m + L.keys_out);
     auto *idx_in = reinterpret_cast<int32_t *>(m + L.idx_in);
     auto *perm = reinterpret_cast<int32_t *>(m + L.perm);
-    auto *cell = reinterpret_cast<int32_t *>(m + L.cell);
+    int32_t *cell = c->m_cell_next;  // the current base cells stay intact until the samples pass the checks
     int *bad = reinterpret_cast<int *>(m + L.misc);
-    int32_t *nband_dev = reinterpret_cast<int32_t *>(m + L.misc + 16);
+    int32_t *counts = reinterpret_cast<int32_t *>(m + L.misc + 16);  // band nodes, runs
     hipStream_t st = c->stream;
 
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, bad);
@@ -558,14 +651,14 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
     if (*bad) return hipSuccess;
 
     size_t sort_bytes = L.sort_tmp_bytes;
-    e = hipcub::DeviceRadixSort::SortPairs(m + L.sort_tmp, sort_bytes, keys_in, keys_out, idx_in, perm, (int)n, 0,
-                                           key_bits(c), st);
+    e = sort_samples(m + L.sort_tmp, sort_bytes, keys_in, keys_out, idx_in, perm, n, key_bits(c), st);
     if (e != hipSuccess) return e;
     c->m_pos = reinterpret_cast<float *>(m + L.pos);
     c->m_ub = reinterpret_cast<float *>(m + L.ub);
     c->m_area = reinterpret_cast<float *>(m + L.area);
     c->m_gain = reinterpret_cast<float *>(m + L.gain);
     c->m_slot = reinterpret_cast<int32_t *>(m + L.slot);
+    c->m_cell_next = c->m_cell;
     c->m_cell = cell;
     c->m_perm = perm;
     c->tile_mask = reinterpret_cast<uint64_t *>(m + L.tile_mask);
@@ -586,13 +679,6 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
     size_t scan_bytes = L.scan_tmp_bytes;
     e = hipcub::DeviceScan::ExclusiveSum(m + L.scan_tmp, scan_bytes, cnt, c->tile_start, (int)c->g.W, st);
     if (e != hipSuccess) return e;
-    // band size = start[W-1] + count[W-1]
-    int32_t tail[2];
-    if ((e = hipMemcpyAsync(&tail[0], c->tile_start + (c->g.W - 1), 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(&tail[1], cnt + (c->g.W - 1), 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    (void)nband_dev;
-    c->nband = (int64_t)tail[0] + tail[1];
     hipLaunchKernelGGL(k_band_list, grid_for(c->g.W), dim3(256), 0, st, mg, c->g.W,
                        reinterpret_cast<const unsigned long long *>(c->tile_mask), c->tile_start, c->band_cell);
     hipLaunchKernelGGL(k_mk_slots, grid_for(n), dim3(256), 0, st, mg, n, c->m_pos,
@@ -609,15 +695,53 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
     e = hipcub::DeviceScan::ExclusiveSum(m + L.scan_tmp, scan_bytes, head, rid, (int)n, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_run_start, grid_for(n), dim3(256), 0, st, n, head, rid, c->run_start);
-    if ((e = hipMemcpyAsync(&tail[0], rid + (n - 1), 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(&tail[1], head + (n - 1), 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    c->nruns = (int64_t)tail[0] + tail[1];
-    hipLaunchKernelGGL(k_fill_i32, grid_for(8 * c->nband), dim3(256), 0, st, c->band_src, 8 * c->nband, -1);
-    hipLaunchKernelGGL(k_band_src, grid_for(c->nruns), dim3(256), 0, st, c->nruns, n, c->nband, c->run_start,
-                       c->m_slot, c->band_src);
+    hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, st, c->g.W, c->tile_start, cnt, n, rid, head, counts);
+    hipLaunchKernelGGL(k_clear_band_src, dim3(1024), dim3(256), 0, st, c->band_src, counts);
+    hipLaunchKernelGGL(k_band_src, grid_for(n), dim3(256), 0, st, n, counts, c->run_start, c->m_slot, c->band_src);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return hipStreamSynchronize(st);
+    int32_t got[2];
+    if ((e = hipMemcpyAsync(got, counts, sizeof(got), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    c->nband = got[0];
+    c->nruns = got[1];
+    return hipSuccess;
+}
+
+hipError_t solids_store_body(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area,
+                             const float *gain)
+{
+    SolidsLayout L;
+    hipError_t e = solids_layout(c, n, &L);
+    if (e != hipSuccess) return e;
+    char *m = c->mws;
+    c->m_cell = reinterpret_cast<int32_t *>(m + L.cell);
+    c->m_cell_next = reinterpret_cast<int32_t *>(m + L.cell2);
+    c->b_xyz = reinterpret_cast<float *>(m + L.body_xyz);
+    c->b_ub = reinterpret_cast<float *>(m + L.body_ub);
+    c->b_area = reinterpret_cast<float *>(m + L.body_area);
+    c->b_gain = reinterpret_cast<float *>(m + L.body_gain);
+    c->w_xyz = reinterpret_cast<float *>(m + L.world_xyz);
+    c->w_ub = reinterpret_cast<float *>(m + L.world_ub);
+    hipLaunchKernelGGL(k_body_store, grid_for(n), dim3(256), 0, c->stream, n, xyz, ub, area, gain, c->b_xyz, c->b_ub,
+                       c->b_area, c->b_gain);
+    return hipGetLastError();
+}
+
+hipError_t solids_pose(lbm_ctx *c, const double R[9], const double o[3], const double v[3], const double w[3],
+                       int *bad_host)
+{
+    Pose P{};
+    for (int k = 0; k < 9; ++k) P.R[k] = R[k];
+    for (int a = 0; a < 3; ++a) {
+        P.o[a] = o[a];
+        P.v[a] = v[a];
+        P.w[a] = w[a];
+    }
+    const int64_t n = c->nm;
+    hipLaunchKernelGGL(k_pose, grid_for(n), dim3(256), 0, c->stream, n, P, c->b_xyz, c->b_ub, c->w_xyz, c->w_ub);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return solids_setup(c, n, c->w_xyz, c->w_ub, c->b_area, c->b_gain, bad_host);
 }
 
 __global__ void k_gather_gain(int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ gain,
@@ -629,6 +753,8 @@ __global__ void k_gather_gain(int64_t n, const int32_t *__restrict__ perm, const
 
 hipError_t launch_set_gains(lbm_ctx *c, const float *gain)
 {
+    const hipError_t e = launch_copy(c, c->b_gain, gain, (size_t)c->nm * 4);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather_gain, grid_for(c->nm), dim3(256), 0, c->stream, c->nm, c->m_perm, gain, c->m_gain);
     return hipGetLastError();
 }

@@ -29,8 +29,8 @@ struct lbm_ctx {
     double *red_part = nullptr;  // [red_blocks][4]
     int *red_flag = nullptr;     // non-finite count
     double *red_out = nullptr;   // [4]
-    double *ftot = nullptr;      // [3] IB force of the last step
-    double *ftot_eval = nullptr; // [3] IB force evaluated by lbm_ib_force_eval
+    double *ftot = nullptr;      // [6] IB force and torque of the last step
+    double *ftot_eval = nullptr; // [6] IB force and torque evaluated by lbm_ib_force_eval
     int red_blocks = 0;
     // relaxation rates
     double s_nu = 1, s_b = 1, s_h[4] = {1, 1, 1, 1};
@@ -41,14 +41,18 @@ struct lbm_ctx {
     size_t mws_bytes = 0;
     float *m_pos = nullptr, *m_ub = nullptr, *m_area = nullptr, *m_gain = nullptr;  // sorted order
     int32_t *m_slot = nullptr;     // [8][nm] band slot of each stencil node
-    int32_t *m_cell = nullptr;     // [nm] base cell, input order
+    int32_t *m_cell = nullptr;     // [nm] base cell, input order (one of two buffers)
+    int32_t *m_cell_next = nullptr;// [nm] the other buffer, written by the next placement
+    float *b_xyz = nullptr, *b_ub = nullptr, *b_area = nullptr, *b_gain = nullptr;  // body samples, input order
+    float *w_xyz = nullptr, *w_ub = nullptr;  // placed samples, input order (staging for a new pose)
+    double pose_o[3] = {0, 0, 0};  // reference point of the torque (the pose origin)
     int32_t *m_perm = nullptr;     // [nm] input index of sorted sample k
     uint64_t *tile_mask = nullptr; // [W]
     int32_t *tile_start = nullptr; // [W]
     int32_t *band_cell = nullptr;  // [nband]
     void *band_ru = nullptr;       // [nband] real4 (rho, u)
     void *band_force = nullptr;    // [nband] real4 (g, 0)
-    double *ib_part = nullptr;     // [ceil(nruns/256)][4] per-block force partials
+    double *ib_part = nullptr;     // [ceil(nruns/256)][8] per-block force and torque partials
     int64_t nruns = 0;             // runs of samples sharing a base cell (sorted order)
     int32_t *run_start = nullptr;  // [nruns + 1] first sorted sample of each run
     void *run_sum = nullptr;       // [8][nruns] real4: a K_d g summed over the run, per stencil offset d
@@ -70,6 +74,7 @@ struct SolidsLayout {
     size_t pos, ub, area, gain, slot, cell, perm, keys_in, keys_out, idx_in, sort_tmp, sort_tmp_bytes;
     size_t tile_mask, tile_start, tile_count, scan_tmp, scan_tmp_bytes, band_cell, band_ru, band_force, ib_part, misc;
     size_t run_head, run_id, run_start, run_sum, band_src;
+    size_t cell2, body_xyz, body_ub, body_area, body_gain, world_xyz, world_ub;
     size_t total;
 };
 hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L);
@@ -87,6 +92,11 @@ hipError_t launch_zero(lbm_ctx *c, void *dst, size_t bytes);
 hipError_t launch_scalar_io(lbm_ctx *c, float *dst, const float *src, bool to_state);
 hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area, const float *gain,
                         int *bad_count_host);
+// body copy of the caller's samples (lbm_set_solids) and a rigid placement of them (lbm_set_pose)
+hipError_t solids_store_body(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area,
+                             const float *gain);
+hipError_t solids_pose(lbm_ctx *c, const double R[9], const double o[3], const double v[3], const double w[3],
+                       int *bad_count_host);
 hipError_t launch_solid_maps(lbm_ctx *c, uint8_t *flags, int32_t *cell, int32_t *perm);
 hipError_t launch_set_gains(lbm_ctx *c, const float *gain);
 

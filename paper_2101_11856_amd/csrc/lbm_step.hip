@@ -2,7 +2,7 @@
 //   k_band      (a)+(b) on the immersed-boundary band only: pull + rho, u
 //   k_ib_run    (c) interpolation and penalty force per sample; per run of
 //               samples sharing a base cell, the 8 spreading sums
-//   k_ib_total  (c) FP64 total force from per-block partials, in order
+//   k_ib_total  (c) FP64 total force and torque from per-block partials, in order
 //   k_spread    (c) spreading completed: each band node gathers its run sums
 //   k_fused     (a)+(b)+(d)+(e) for every node: pull with face rules, rho and
 //               u, band force, central-moment collision, store
@@ -203,7 +203,8 @@ template <typename R> struct IbParams {
     const int32_t *__restrict__ slot;       // [8][n]
     const R4 *__restrict__ band_ru;
     R4 *__restrict__ run_sum;               // [8][nruns]
-    double *__restrict__ part;              // [gridDim.x][4] per-block force totals
+    double *__restrict__ part;              // [gridDim.x][8] per-block force and torque totals
+    double ox, oy, oz;                      // reference point of the torque
 };
 
 template <typename R>
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(256) k_ib_run(const IbParams<R> P)
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t n = P.n;
-    double tot[3] = {0.0, 0.0, 0.0};
+    double tot[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // force, then torque about (ox, oy, oz)
     if (r < P.nruns) {
         const int64_t k0 = P.run_start[r], k1 = P.run_start[r + 1];
         R4 node[8];
@@ -224,10 +225,11 @@ __global__ void __launch_bounds__(256) k_ib_run(const IbParams<R> P)
         for (int d = 0; d < 8; ++d) acc[d][0] = acc[d][1] = acc[d][2] = (R)0;
         for (int64_t k = k0; k < k1; ++k) {
             R t[3];
+            float p[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const float p = P.pos[a * n + k];
-                t[a] = (R)(p - floorf(p));
+                p[a] = P.pos[a * n + k];
+                t[a] = (R)(p[a] - floorf(p[a]));
             }
             R K[8], rs = 0, us[3] = {0, 0, 0};
 #pragma unroll
@@ -246,6 +248,11 @@ __global__ void __launch_bounds__(256) k_ib_run(const IbParams<R> P)
                 aG[a] = ag * ((R)P.ub[a * n + k] - us[a]);
                 tot[a] += (double)aG[a];
             }
+            // Alg. 2 (c) torque: (x_s - o) x (a_s g_s), lever arm in FP64
+            const double rx = (double)p[0] - P.ox, ry = (double)p[1] - P.oy, rz = (double)p[2] - P.oz;
+            tot[3] += ry * (double)aG[2] - rz * (double)aG[1];
+            tot[4] += rz * (double)aG[0] - rx * (double)aG[2];
+            tot[5] += rx * (double)aG[1] - ry * (double)aG[0];
 #pragma unroll
             for (int d = 0; d < 8; ++d)
 #pragma unroll
@@ -261,19 +268,19 @@ __global__ void __launch_bounds__(256) k_ib_run(const IbParams<R> P)
             P.run_sum[(int64_t)d * P.nruns + r] = v;
         }
     }
-    // FP64 total force: wave reduction, then one partial per block (no
-    // same-address atomics; the partials are summed in order afterwards)
-    __shared__ double wsum[4][3];
+    // FP64 total force and torque: wave reduction, then one partial per block
+    // (no same-address atomics; the partials are summed in order afterwards)
+    __shared__ double wsum[4][6];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) tot[a] += __shfl_down(tot[a], off, 64);
+        for (int a = 0; a < 6; ++a) tot[a] += __shfl_down(tot[a], off, 64);
     if (lane == 0)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) wsum[threadIdx.x >> 6][a] = tot[a];
+        for (int a = 0; a < 6; ++a) wsum[threadIdx.x >> 6][a] = tot[a];
     __syncthreads();
-    if (threadIdx.x < 3)
-        P.part[4 * blockIdx.x + threadIdx.x] =
+    if (threadIdx.x < 6)
+        P.part[8 * blockIdx.x + threadIdx.x] =
             wsum[0][threadIdx.x] + wsum[1][threadIdx.x] + wsum[2][threadIdx.x] + wsum[3][threadIdx.x];
 }
 
@@ -299,24 +306,24 @@ __global__ void __launch_bounds__(256) k_spread(int64_t nband, int64_t nruns, co
     band_force[j] = g;
 }
 
-// ordered sum of the per-block force partials (deterministic FP64 total)
+// ordered sum of the per-block force and torque partials (deterministic FP64 totals)
 __global__ void __launch_bounds__(256) k_ib_total(const double *__restrict__ part, int nblk, double *__restrict__ ftot)
 {
-    __shared__ double sh[3][256];
-    double acc[3] = {0, 0, 0};
+    __shared__ double sh[6][256];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblk; b += 256)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) acc[a] += part[4 * b + a];
+        for (int a = 0; a < 6; ++a) acc[a] += part[8 * b + a];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) sh[a][threadIdx.x] = acc[a];
+    for (int a = 0; a < 6; ++a) sh[a][threadIdx.x] = acc[a];
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + s];
+            for (int a = 0; a < 6; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x < 3) ftot[threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x < 6) ftot[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -403,6 +410,9 @@ template <int ST> static hipError_t band_ib_st(lbm_ctx *c, const void *state, do
     Q.band_ru = static_cast<const R4 *>(c->band_ru);
     Q.run_sum = static_cast<R4 *>(c->run_sum);
     Q.part = c->ib_part;
+    Q.ox = c->pose_o[0];
+    Q.oy = c->pose_o[1];
+    Q.oz = c->pose_o[2];
     const int nblk = (int)((c->nruns + 255) / 256);
     hipLaunchKernelGGL((k_ib_run<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
     hipLaunchKernelGGL(k_ib_total, dim3(1), dim3(256), 0, c->stream, c->ib_part, nblk, ftot);

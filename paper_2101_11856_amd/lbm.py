@@ -67,6 +67,11 @@ _SIG = {
     "lbm_conserved": [_vp, C.POINTER(C.c_double)],
     "lbm_ib_force": [_vp, C.POINTER(C.c_double)],
     "lbm_ib_force_eval": [_vp, C.POINTER(C.c_double)],
+    "lbm_ib_torque": [_vp, C.POINTER(C.c_double)],
+    "lbm_set_pose": [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                     C.POINTER(C.c_double)],
+    "lbm_set_body": [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                     C.POINTER(C.c_double), C.POINTER(C.c_double)],
     "lbm_solid_maps": [_vp, _vp, _vp, _vp],
     "lbm_state_bytes": [_vp, C.POINTER(_sz)],
     "lbm_checkpoint": [_vp, _vp],
@@ -97,6 +102,15 @@ lib = _L
 def _check(status: int, ctx=None):
     if status != 0:
         raise LbmError(status, _L.lbm_last_error(ctx).decode())
+
+
+def _pose_args(R, o, v, w):
+    def dbl(a, k, what):
+        a = np.asarray(a, dtype=np.float64).reshape(-1)
+        if a.size != k:
+            raise ValueError(f"{what} needs {k} values, got {a.size}")
+        return (C.c_double * k)(*a.tolist())
+    return dbl(R, 9, "R"), dbl(o, 3, "o"), dbl(v, 3, "v"), dbl(w, 3, "w")
 
 
 def _ptr(t: torch.Tensor | None):
@@ -235,22 +249,50 @@ class Solver:
         _check(_L.lbm_get_scalar(self._h, _ptr(s)), self._h)
         return s
 
-    def set_solids(self, xyz, ub=None, area=None, gain=None):
+    def _samples(self, xyz, ub, area, gain):
         f32 = lambda t: None if t is None else torch.as_tensor(t, device=self.device).to(torch.float32).contiguous()
         xyz, ub, area, gain = f32(xyz), f32(ub), f32(area), f32(gain)
         n = 0 if xyz is None else int(xyz.shape[1])
         if n == 0:
-            _check(_L.lbm_set_solids(self._h, 0, None, None, None, None, None, 0), self._h)
-            self.n_markers = 0
-            return
+            return 0, None
+        if xyz.shape != (3, n):
+            raise ValueError(f"sample positions must be [3, n], got {tuple(xyz.shape)}")
         if ub is None:
             ub = torch.zeros((3, n), dtype=torch.float32, device=self.device)
+        _need(ub, 3 * n * 4, "ub ([3, n])")
+        _need(area, n * 4, "area ([n])")
+        _need(gain, n * 4, "gain ([n])")
         nb = C.c_size_t()
         _check(_L.lbm_solids_ws_size(self._h, n, C.byref(nb)), self._h)
         self._mws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
-        _check(_L.lbm_set_solids(self._h, n, _ptr(xyz), _ptr(ub), _ptr(area), _ptr(gain), _ptr(self._mws),
-                                 self._mws.numel()), self._h)
+        return n, (_ptr(xyz), _ptr(ub), _ptr(area), _ptr(gain), _ptr(self._mws), self._mws.numel())
+
+    def set_solids(self, xyz, ub=None, area=None, gain=None):
+        n, args = self._samples(xyz, ub, area, gain)
+        self.n_markers = 0
+        if n == 0:
+            _check(_L.lbm_set_solids(self._h, 0, None, None, None, None, None, 0), self._h)
+            return
+        _check(_L.lbm_set_solids(self._h, n, *args), self._h)
         self.n_markers = n
+
+    def set_body(self, X, ub, area, gain, R, o, v=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0)):
+        """Samples in body coordinates, placed at the pose (R, o, v, w) (see lbm_set_body)."""
+        n, args = self._samples(X, ub, area, gain)
+        if n == 0:
+            raise ValueError("set_body needs at least one sample")
+        self.n_markers = 0
+        _check(_L.lbm_set_body(self._h, n, *args, *_pose_args(R, o, v, w)), self._h)
+        self.n_markers = n
+
+    def set_pose(self, R, o, v=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0)):
+        """Place the body samples at o + R X (rigid motion, see lbm_set_pose)."""
+        _check(_L.lbm_set_pose(self._h, *_pose_args(R, o, v, w)), self._h)
+
+    def ib_torque(self) -> np.ndarray:
+        out = (C.c_double * 3)()
+        _check(_L.lbm_ib_torque(self._h, out), self._h)
+        return np.array(out[:])
 
     def step(self, n: int = 1):
         _check(_L.lbm_step(self._h, int(n)), self._h)

@@ -17,7 +17,8 @@ available; these generators stand in for them:
     (flow past an immersed sphere, 512x128x128),
   * a field of axis-aligned boxes sampled on walls and roofs (city blocks,
     1200x250x840),
-  * a cylinder along z with a modal inlet profile (adjoint channel).
+  * a cylinder along z with a modal inlet profile (adjoint channel),
+  * a torus in prescribed rigid rotation (the rotating torus of Sec. 5).
 """
 from __future__ import annotations
 
@@ -108,6 +109,32 @@ def fibonacci_sphere(n: int, radius: float, center) -> np.ndarray:
     p = np.stack([r * np.cos(phi), r * np.sin(phi), zc]) * radius
     p += np.asarray(center, dtype=np.float64)[:, None]
     return p.astype(np.float32)
+
+
+def torus_body(major: float, minor: float, per_length: float = 3.0):
+    """Body-frame samples of a torus about the z axis, centred on the origin:
+    rings of the tube at n_t = round(2 pi major k) angles theta, each with
+    n_p = round(2 pi minor k) samples (k = per_length), every other ring
+    turned by half a step.  Area weight of a sample: the surface element
+    minor (major + minor cos phi) dtheta dphi, so the weights sum to the
+    torus area 4 pi^2 major minor.  Returns (xyz float32 [3, n], area float32 [n])."""
+    nt = max(3, int(round(2.0 * math.pi * major * per_length)))
+    nph = max(3, int(round(2.0 * math.pi * minor * per_length)))
+    dt, dp = 2.0 * math.pi / nt, 2.0 * math.pi / nph
+    th = np.repeat(np.arange(nt) * dt, nph)
+    ph = (np.tile(np.arange(nph), nt) + 0.5 * (np.repeat(np.arange(nt), nph) % 2)) * dp
+    ring = major + minor * np.cos(ph)
+    xyz = np.stack([ring * np.cos(th), ring * np.sin(th), minor * np.sin(ph)])
+    area = minor * ring * dt * dp
+    return xyz.astype(np.float32), area.astype(np.float32)
+
+
+def rotation(axis, angle: float) -> np.ndarray:
+    """Rotation matrix by `angle` (radians, right-handed) about `axis`."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    return np.eye(3) + math.sin(angle) * K + (1.0 - math.cos(angle)) * (K @ K)
 
 
 def random_box(n: int, lo, hi, seed: int) -> np.ndarray:

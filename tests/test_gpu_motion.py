@@ -1,0 +1,151 @@
+"""GPU parity of moving solids: the per-step rigid placement of the samples
+with re-sorting and re-banding (lbm_set_pose), and the FP64 total torque,
+against the oracle's rigid_pose + set_markers + step on the same kinematics.
+
+Gates: FP32 rel-L2 on rho and u <= 1e-5, force and torque <= 1e-4 (FP32
+per-sample forces summed in another order); FP64 to round-off; the sample
+maps after every placement bit-exact (both sides round the placed position
+to FP32 from the same FP64 operations).  The library keeps sample data in
+FP32 (the sample arrays of its interface), so the oracle is given the placed
+boundary velocities rounded to FP32 as well."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2101_11856_amd import synth
+from tests.gpu_cases import NS, P, gpu_solver, rel_l2, say, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_11856_amd import lbm  # noqa: F401  (fails loudly if liblbm.so is missing)
+    yield
+
+
+SHAPE = (80, 28, 30)                       # nx, ny, nz: one full 64-node row segment and a ragged 16-node tail
+FACES = (P, P, NS, NS, P, P)
+TILT = synth.rotation((1.0, 0.0, 0.0), 0.4)
+AXIS = np.array([0.2, 0.1, 1.0])
+RATE = 0.01                                # rad per step: rim speed 0.08
+V = np.array([0.05, 0.0, 0.0])
+O0 = np.array([40.0, 14.0, 15.0])
+
+
+def _body():
+    X, area = synth.torus_body(6.0, 2.0, per_length=2.0)
+    rng = np.random.default_rng(21)
+    gain = rng.uniform(0.8, 1.2, X.shape[1]).astype(np.float32)
+    ub = (0.002 * rng.standard_normal(X.shape)).astype(np.float32)   # body-frame surface velocity
+    return X, ub, area, gain
+
+
+def _pose(t):
+    R = synth.rotation(AXIS, RATE * t) @ TILT
+    return R, O0 + V * t, V, RATE * AXIS / np.linalg.norm(AXIS)
+
+
+def _flow(nx, ny, nz):
+    rng = np.random.default_rng(22)
+    rho = (1.0 + 1e-3 * rng.standard_normal((nz, ny, nx))).astype(np.float32)
+    u = (0.005 * rng.standard_normal((3, nz, ny, nx))).astype(np.float32)
+    return rho, u
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_moving_torus_matches_oracle(storage):
+    nx, ny, nz = SHAPE
+    steps = 12
+    say(f"moving torus {SHAPE} {storage}, {steps} steps")
+    X, ub, area, gain = _body()
+    rho, u = _flow(nx, ny, nz)
+    S = O.OracleSim(nx, ny, nz, 0.05, faces=FACES)
+    S.init_equilibrium(rho.astype(np.float64), u.astype(np.float64))
+    real = np.float64 if storage == "f64" else np.float32
+    s = gpu_solver(nx, ny, nz, 0.05, storage=storage, faces=FACES)
+    s.init_equilibrium(rho.astype(real), u.astype(real))
+    s.set_body(X, ub, area, gain, *_pose(0))
+    fgate, tol = (1e-11, 1e-12) if storage == "f64" else (1e-4, 1e-5)
+    worst_F = worst_T = 0.0
+    for t in range(steps):
+        R, o, v, w = _pose(t)
+        xyz, ubw = O.rigid_pose(X, ub, R, o, v, w)
+        S.set_markers(xyz, ubw.astype(np.float32).astype(np.float64), area.astype(np.float64),
+                      gain.astype(np.float64))
+        S.step(1)
+        s.set_pose(R, o, v, w)
+        s.step(1)
+        F_ref, T_ref = S.last_force(), S.last_torque(o)
+        worst_F = max(worst_F, rel_l2(s.ib_force(), F_ref))
+        worst_T = max(worst_T, rel_l2(s.ib_torque(), T_ref))
+        if t in (0, steps - 1):
+            fl, cell, perm = (to_np(a).astype(np.int64) for a in s.solid_maps())
+            fl_r, cell_r, perm_r = S.maps()
+            assert np.array_equal(fl, fl_r) and np.array_equal(cell, cell_r) and np.array_equal(perm, perm_r), t
+    r_ref, u_ref = S.macros()
+    r, uu = (to_np(a) for a in s.macros())
+    e_u, e_r = rel_l2(uu, u_ref), rel_l2(r, r_ref)
+    say(f"  rel-L2 u={e_u:.3e} rho={e_r:.3e}; worst force {worst_F:.3e} torque {worst_T:.3e}")
+    assert e_u <= tol and e_r <= tol
+    assert worst_F <= fgate and worst_T <= fgate
+
+
+def test_identity_pose_reproduces_static_samples():
+    nx, ny, nz = SHAPE
+    say("identity pose vs static samples")
+    X, ub, area, gain = _body()
+    Xw = (X.astype(np.float64) + O0[:, None]).astype(np.float32)      # already in the domain
+    rho, u = _flow(nx, ny, nz)
+    runs = []
+    for posed in (False, True):
+        s = gpu_solver(nx, ny, nz, 0.05, faces=FACES)
+        s.init_equilibrium(rho, u)
+        s.set_solids(Xw, ub, area, gain)
+        if posed:
+            s.set_pose(np.eye(3), (0.0, 0.0, 0.0))
+        s.step(5)
+        runs.append((s.get_populations().clone(), s.ib_force(), s.ib_torque(), s.solid_maps()))
+    (fa, Fa, Ta, ma), (fb, Fb, Tb, mb) = runs
+    assert torch.equal(fa, fb)
+    assert np.array_equal(Fa, Fb) and np.array_equal(Ta, Tb)
+    assert all(torch.equal(x, y) for x, y in zip(ma, mb))
+
+
+def test_rejected_pose_keeps_the_previous_one():
+    from paper_2101_11856_amd.lbm import LbmError
+    nx, ny, nz = SHAPE
+    say("rejected pose")
+    X, ub, area, gain = _body()
+    rho, u = _flow(nx, ny, nz)
+    runs = []
+    for attempt in (False, True):
+        s = gpu_solver(nx, ny, nz, 0.05, faces=FACES)
+        s.init_equilibrium(rho, u)
+        s.set_body(X, ub, area, gain, *_pose(3))
+        if attempt:
+            R, o, v, w = _pose(3)
+            with pytest.raises(LbmError):
+                s.set_pose(R, o + np.array([0.0, 20.0, 0.0]), v, w)    # y leaves the walled axis
+        s.step(4)
+        runs.append((s.get_populations().clone(), s.ib_torque(), s.solid_maps()))
+    assert torch.equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    assert all(torch.equal(x, y) for x, y in zip(runs[0][2], runs[1][2]))
+
+
+def test_pose_needs_samples_inside_the_domain():
+    from paper_2101_11856_amd.lbm import LbmError
+    s = gpu_solver(16, 16, 16, 0.05, faces=FACES)
+    with pytest.raises(LbmError):
+        s.set_pose(np.eye(3), (8.0, 8.0, 8.0))                       # no samples yet
+    with pytest.raises(ValueError):
+        s.set_pose(np.eye(2), (8.0, 8.0, 8.0))
+    X, ub, area, gain = _body()
+    with pytest.raises(LbmError):
+        s.set_body(X, ub, area, gain, np.eye(3), (8.0, 8.0, 8.0))   # radius 8 reaches y = 0 and 16
+    assert s.n_markers == 0
+    s.step(1)
+    assert np.array_equal(s.ib_force(), np.zeros(3)) and np.array_equal(s.ib_torque(), np.zeros(3))

@@ -76,3 +76,17 @@ def test_cylinder_and_inlet_modes():
     prof = synth.inlet_profile(64, 64, a)
     assert prof.shape == (3, 64, 64) and np.allclose(prof[1:], 0)
     assert np.allclose(prof[0], 0.04 + np.tensordot(a, B, 1))
+
+
+def test_torus_body_and_rotation():
+    import math
+    from scipy.spatial.transform import Rotation
+    xyz, area = synth.torus_body(12.0, 4.0, per_length=2.0)
+    p = xyz.astype(np.float64)
+    tube = np.hypot(np.hypot(p[0], p[1]) - 12.0, p[2])     # distance to the tube's centre circle
+    assert np.allclose(tube, 4.0, atol=1e-5)
+    assert abs(area.astype(np.float64).sum() - 4 * math.pi ** 2 * 12.0 * 4.0) < 1e-4 * 4 * math.pi ** 2 * 48
+    axis, ang = np.array([0.3, -0.5, 0.8]), 0.7
+    R = synth.rotation(axis, ang)
+    ref = Rotation.from_rotvec(axis / np.linalg.norm(axis) * ang).as_matrix()
+    assert np.allclose(R, ref, atol=1e-14)
