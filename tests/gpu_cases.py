@@ -46,3 +46,26 @@ def gpu_solver(nx, ny, nz, nu, storage="f32", **kw):
 
 def to_np(t):
     return t.detach().to("cpu").double().numpy()
+
+
+def smooth_fields(nx, ny, nz):
+    """Non-trivial smooth initial fields (float32, separable products), so that
+    the first step changes every node: rho = 1 + 1e-3 a, u = (0.05 + 0.01 b,
+    0.005 c, 0.005 d), scalar in [0, 1]."""
+    X = np.arange(nx, dtype=np.float32)
+    Y = np.arange(ny, dtype=np.float32)
+    Z = np.arange(nz, dtype=np.float32)
+    two_pi = np.float32(2 * np.pi)
+
+    def sep(fx, fy, fz):
+        return (fz[:, None, None] * fy[None, :, None]) * fx[None, None, :]
+
+    sx, cy, sz = np.sin(two_pi * 3 * X / nx), np.cos(two_pi * 2 * Y / ny), np.sin(two_pi * 5 * Z / nz)
+    cx, sy, cz = np.cos(two_pi * 4 * X / nx), np.sin(two_pi * 3 * Y / ny), np.cos(two_pi * 2 * Z / nz)
+    rho = np.float32(1) + np.float32(1e-3) * sep(sx, sy, cz)
+    u = np.empty((3, nz, ny, nx), np.float32)
+    u[0] = np.float32(0.05) + np.float32(0.01) * sep(cx, cy, sz)
+    u[1] = np.float32(0.005) * sep(sx, cy, cz)
+    u[2] = np.float32(0.005) * sep(cx, sy, sz)
+    sc = np.float32(0.5) + np.float32(0.5) * sep(sx, cy, cz)
+    return rho, u, sc

@@ -8,7 +8,7 @@ import torch
 
 from oracle import oracle as O
 from paper_2101_11856_amd import synth
-from tests.gpu_cases import FS, IN, NS, OUT, P, gpu_solver, rel_l2, say, to_np
+from tests.gpu_cases import FS, IN, NS, OUT, P, gpu_solver, rel_l2, say, smooth_fields, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -169,29 +169,6 @@ def test_passive_scalar_many_steps():
     assert e_s <= 1e-5
 
 
-def _smooth_fields(nx, ny, nz):
-    """Non-trivial smooth initial fields (float32, separable products), so that
-    the first step changes every node: rho = 1 + 1e-3 a, u = (0.05 + 0.01 b,
-    0.005 c, 0.005 d), scalar in [0, 1]."""
-    X = np.arange(nx, dtype=np.float32)
-    Y = np.arange(ny, dtype=np.float32)
-    Z = np.arange(nz, dtype=np.float32)
-    two_pi = np.float32(2 * np.pi)
-
-    def sep(fx, fy, fz):
-        return (fz[:, None, None] * fy[None, :, None]) * fx[None, None, :]
-
-    sx, cy, sz = np.sin(two_pi * 3 * X / nx), np.cos(two_pi * 2 * Y / ny), np.sin(two_pi * 5 * Z / nz)
-    cx, sy, cz = np.cos(two_pi * 4 * X / nx), np.sin(two_pi * 3 * Y / ny), np.cos(two_pi * 2 * Z / nz)
-    rho = np.float32(1) + np.float32(1e-3) * sep(sx, sy, cz)
-    u = np.empty((3, nz, ny, nx), np.float32)
-    u[0] = np.float32(0.05) + np.float32(0.01) * sep(cx, cy, sz)
-    u[1] = np.float32(0.005) * sep(sx, cy, cz)
-    u[2] = np.float32(0.005) * sep(cx, sy, sz)
-    sc = np.float32(0.5) + np.float32(0.5) * sep(sx, cy, cz)
-    return rho, u, sc
-
-
 def test_city_full_size_maps_and_sampled_nodes():
     """City 1200x250x840 at full size (252M nodes, 3.86M samples), in the
     launch configuration the benchmark times.  The FP64 oracle cannot step the
@@ -210,7 +187,7 @@ def test_city_full_size_maps_and_sampled_nodes():
     h_sc = 50
     xyz, ub, area, gain = synth.city_markers(synth.city_boxes())
     n = xyz.shape[1]
-    rho, u, sc0 = _smooth_fields(nx, ny, nz)
+    rho, u, sc0 = smooth_fields(nx, ny, nz)
     s = gpu_solver(nx, ny, nz, 1e-5, faces=faces, u_in=(0.05, 0, 0), scalar=True, scalar_inlet_height=h_sc)
     s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
     s.set_scalar(torch.from_numpy(sc0).cuda())
