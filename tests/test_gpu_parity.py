@@ -300,4 +300,8 @@ def test_binding_refuses_unsafe_buffers():
     with pytest.raises(ValueError):
         s.adjoint_seed_force((1.0, 0.0, 0.0), torch.zeros((3, nz, ny), dtype=torch.float64))   # host memory
     s.adjoint_step(2, tape, s.new_grad_inlet(), s.new_grad_gain())             # the valid call still works
+    with pytest.raises(ValueError):
+        s.set_solids(np.ascontiguousarray(xyz[:, keep].T))                      # [n, 3] instead of [3, n]
+    with pytest.raises(ValueError):
+        s.set_solids(xyz[:, keep], area=np.ones(1, np.float32))                 # area shorter than n
     torch.cuda.synchronize()
