@@ -27,9 +27,9 @@ if ROOT not in sys.path:
 METRIC = "MLUPS (D3Q27 ACM-MRT+IBM), % HBM roofline; FP16-store vs FP32 at stated error"
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "k_fused_turbulence256_f32_counters.txt")
-# sources that decide the fused kernel's code and memory layout, and its build flags
+# sources that decide the fused kernel's code and memory layout, the calibration copy, and the build flags
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2101_11856_amd", "csrc", f)
-                  for f in ("lbm_step.hip", "lbm_internal.hpp", "lbm_api.hip", "lbm_ctx.hpp")]
+                  for f in ("lbm_step.hip", "lbm_internal.hpp", "lbm_api.hip", "lbm_ctx.hpp", "lbm_aux.hip")]
 KERNEL_SOURCES.append(os.path.join(ROOT, "paper_2101_11856_amd", "build.py"))
 
 
@@ -71,6 +71,24 @@ def timed_steps(solver, steps, warmup):
     return e0.elapsed_time(e1) / 1e3
 
 
+def measured_copy(solver, reps=5):
+    """Device copy bandwidth on this GPU: the library's plain 16-byte-per-lane
+    copy (lbm_checkpoint) of the whole population state, read + write bytes
+    over HIP-event time on the solver's stream."""
+    import torch
+    dst = solver.checkpoint()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(solver.stream)
+    for _ in range(reps):
+        solver.checkpoint(dst)
+    e1.record(solver.stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    return 2 * solver.state_bytes() * reps / t / 1e9
+
+
 def turbulence_solver(n, storage, rho, u):
     from paper_2101_11856_amd import lbm
     s = lbm.Solver(n, n, n, 1e-4, storage=storage)
@@ -101,12 +119,13 @@ def cpu_baseline(rho, u, n, budget_s=20.0):
                       f"turbulence field ({cells} cells, {dt:.1f} s)"}
 
 
-def sphere_workload(steps, warmup):
+def sphere_workload(steps, warmup, storage="f32"):
     import torch
 
     from paper_2101_11856_amd import lbm, synth
     nx, ny, nz = 512, 128, 128
-    s = lbm.Solver(nx, ny, nz, 5e-5, faces=(lbm.INLET, lbm.OUTFLOW, 0, 0, 0, 0), u_in=(0.05, 0.0, 0.0))
+    s = lbm.Solver(nx, ny, nz, 5e-5, faces=(lbm.INLET, lbm.OUTFLOW, 0, 0, 0, 0), u_in=(0.05, 0.0, 0.0),
+                   storage=storage)
     rho, u = synth.uniform(nx, ny, nz, (0.05, 0.0, 0.0))
     s.init_equilibrium(rho, u)
     xyz, ub, area, gain = synth.sphere_scene()
@@ -115,7 +134,7 @@ def sphere_workload(steps, warmup):
     t = timed_steps(s, steps, warmup)
     F = s.ib_force()
     out = {"workload": "flow past an immersed sphere 512x128x128, inlet/outflow, 13000 sphere + 200000 "
-                       "random samples, FP32", "value": round(nx * ny * nz * steps / t / 1e6, 1),
+                       f"random samples, {storage.upper()}", "value": round(nx * ny * nz * steps / t / 1e6, 1),
            "unit": "MLUPS", "ms_per_step": round(1e3 * t / steps, 4), "samples": int(xyz.shape[1]),
            "band_nodes": band, "drag_x": float(-F[0])}
     del s
@@ -261,7 +280,7 @@ def main():
     from paper_2101_11856_amd import synth
 
     if args.profile_pass and args.workload == "sphere":
-        print(json.dumps(sphere_workload(args.steps, args.warmup)), flush=True)
+        print(json.dumps(sphere_workload(args.steps, args.warmup, args.storage)), flush=True)
         return
     if args.profile_pass and args.workload == "moving_torus":
         print(json.dumps(moving_torus_workload(args.steps, args.warmup)), flush=True)
@@ -296,6 +315,7 @@ def main():
     _, u32 = s.macros()
     u32 = u32.cpu().numpy()
     mlups = cells * args.steps / t / 1e6
+    copy_gbs = measured_copy(s)
     t_launch = t / args.steps          # only the fused kernel runs in this workload
     bytes_launch = 27 * 2 * 4 * cells  # algorithmic: read + write 27 FP32 per cell
     achieved = bytes_launch / t_launch / 1e9
@@ -318,7 +338,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / t_launch / 1e9, 1),
-                     "kernel": "k_fused<f32>", "algorithmic_bytes_per_launch": bytes_launch},
+                     "kernel": "k_fused<f32>", "algorithmic_bytes_per_launch": bytes_launch,
+                     "copy_measured_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "mass_drift_rel": float(abs(c1[0] - c0[0]) / c0[0]),
     }
     del s
@@ -355,6 +376,7 @@ def main():
                               "run matches the FP64 oracle to <= 1e-5); the gate's terms are 100 steps"}
         log("sphere run")
         result["ib_sphere"] = sphere_workload(min(args.steps, 2000), min(args.warmup, 10))
+        result["ib_sphere_f16"] = sphere_workload(min(args.steps, 2000), min(args.warmup, 10), "f16")
         for storage in ("f32", "f16"):
             log(f"city run {storage}")
             result[f"city_{storage}"] = city_workload(min(args.steps, 100), min(args.warmup, 5), storage)
