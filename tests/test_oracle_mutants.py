@@ -1,5 +1,6 @@
 """Mutation test of the oracle's pins: each entry plants one plausible mistake
-in a temporary copy of the oracle source (a dropped term, a wrong sign, index
+in a temporary copy of the oracle source (the C file, or the Python rigid
+placement) (a dropped term, a wrong sign, index
 or operand, a misplaced face rule), builds it, and runs the pin suite against
 it; every mutant must make some pin fail.  An unmutated copy built the same
 way must pass, so a broken harness cannot pass for a caught mutant.  The
@@ -69,6 +70,40 @@ MUTANTS = {
 }
 
 
+# mistakes planted in the oracle's Python part (the rigid placement of Alg. 2 (c))
+PY_SRC = os.path.join(ROOT, "oracle", "oracle.py")
+PY_PINS = ["tests/test_oracle_motion.py"]
+PY_MUTANTS = {
+    "pose_rotation_transposed": ("(o[a] + ((R[a, 0] * X[0] + R[a, 1] * X[1]) + R[a, 2] * X[2]))",
+                                 "(o[a] + ((R[0, a] * X[0] + R[1, a] * X[1]) + R[2, a] * X[2]))"),
+    "pose_origin_dropped": ("(o[a] + ((R[a, 0] * X[0] + R[a, 1] * X[1]) + R[a, 2] * X[2]))",
+                            "(((R[a, 0] * X[0] + R[a, 1] * X[1]) + R[a, 2] * X[2]))"),
+    "pose_spin_sign_x": ("ub_w[0] = rot_ub[0] + v[0] + (w[1] * r[2] - w[2] * r[1])",
+                         "ub_w[0] = rot_ub[0] + v[0] - (w[1] * r[2] - w[2] * r[1])"),
+    "pose_body_velocity_not_rotated": ("rot_ub = np.array([(R[a, 0] * ub[0] + R[a, 1] * ub[1]) + R[a, 2] * ub[2] for a in range(3)])",
+                                       "rot_ub = ub"),
+    "pose_lever_from_coordinate_origin": ("r = xyz.astype(np.float64) - o[:, None]", "r = xyz.astype(np.float64)"),
+    "pose_drift_dropped": ("ub_w[1] = rot_ub[1] + v[1] + (w[2] * r[0] - w[0] * r[2])",
+                           "ub_w[1] = rot_ub[1] + (w[2] * r[0] - w[0] * r[2])"),
+}
+
+
+def _run_py_pins(source: str, workdir: str, name: str, library: str) -> subprocess.CompletedProcess:
+    """Pins of the Python part against a copy of the oracle package whose
+    oracle.py is `source`, in a tree of its own (the committed files stay)."""
+    root = os.path.join(workdir, name)
+    os.makedirs(os.path.join(root, "oracle"))
+    os.makedirs(os.path.join(root, "tests"))
+    shutil.copy(os.path.join(ROOT, "oracle", "__init__.py"), os.path.join(root, "oracle", "__init__.py"))
+    with open(os.path.join(root, "oracle", "oracle.py"), "w") as fh:
+        fh.write(source)
+    for f in ["conftest.py", *[os.path.basename(p) for p in PY_PINS]]:
+        shutil.copy(os.path.join(ROOT, "tests", f), os.path.join(root, "tests", f))
+    env = dict(os.environ, LBM_ORACLE_LIBRARY=library, OMP_NUM_THREADS="2")
+    return subprocess.run([sys.executable, "-m", "pytest", *PY_PINS, "-q", "-x", "-p", "no:cacheprovider"],
+                          cwd=root, env=env, capture_output=True, text=True, timeout=600)
+
+
 def _run_pins(source: str, workdir: str, name: str) -> subprocess.CompletedProcess:
     c = os.path.join(workdir, f"{name}.c")
     so = os.path.join(workdir, f"{name}.so")
@@ -92,6 +127,24 @@ def test_every_planted_mistake_fails_a_pin():
         with cf.ThreadPoolExecutor(4) as ex:
             futs = {name: ex.submit(_run_pins, src.replace(old, new), td, name)
                     for name, (old, new) in MUTANTS.items()}
+            survivors = [name for name, fut in futs.items()
+                         if fut.result().returncode == 0 or fut.result().returncode == 5]
+    assert not survivors, f"mutants no pin catches: {survivors}"
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_every_planted_mistake_in_the_placement_fails_a_pin():
+    from oracle import oracle as O
+    library = O.build()
+    src = open(PY_SRC).read()
+    for name, (old, _) in PY_MUTANTS.items():
+        assert src.count(old) == 1, f"mutant {name}: its source text is not found exactly once"
+    with tempfile.TemporaryDirectory() as td:
+        control = _run_py_pins(src, td, "control", library)
+        assert control.returncode == 0, "unmutated copy fails the pins:\n" + control.stdout[-2000:]
+        with cf.ThreadPoolExecutor(4) as ex:
+            futs = {name: ex.submit(_run_py_pins, src.replace(old, new), td, name, library)
+                    for name, (old, new) in PY_MUTANTS.items()}
             survivors = [name for name, fut in futs.items()
                          if fut.result().returncode == 0 or fut.result().returncode == 5]
     assert not survivors, f"mutants no pin catches: {survivors}"
