@@ -45,7 +45,7 @@ class Params(C.Structure):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950) first")
+    raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2101_11856_amd.build (hipcc, gfx950) first")
 
 _L = C.CDLL(LIB_PATH)
 _vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
