@@ -224,7 +224,10 @@ lbm_status lbm_set_gains(lbm_ctx *ctx, const float *gain);
  * adjoint workspace.  Gradients accumulate in FP64.  Reading of the paper: the
  * objective depends on the final state only (drag from lbm_ib_force_eval,
  * velocities from lbm_macros), so the reverse sweep starts from seeds on that
- * state and walks the steps backwards over a tape of forward states. */
+ * state and walks the steps backwards over a tape of forward states.  The
+ * tape holds states, not sample placements: every taped step is
+ * differentiated with the samples where they are when lbm_adjoint_step runs,
+ * so a solid moved by lbm_set_pose during the taped steps is not supported. */
 
 /* Device bytes of the adjoint workspace for the current grid and samples. */
 lbm_status lbm_adjoint_ws_size(const lbm_ctx *ctx, size_t *bytes);
