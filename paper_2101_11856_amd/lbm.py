@@ -252,6 +252,8 @@ class Solver:
     def _samples(self, xyz, ub, area, gain):
         f32 = lambda t: None if t is None else torch.as_tensor(t, device=self.device).to(torch.float32).contiguous()
         xyz, ub, area, gain = f32(xyz), f32(ub), f32(area), f32(gain)
+        if xyz is not None and (xyz.dim() != 2 or xyz.shape[0] != 3):
+            raise ValueError(f"sample positions must be [3, n], got {tuple(xyz.shape)}")
         n = 0 if xyz is None else int(xyz.shape[1])
         if n == 0:
             return 0, None
