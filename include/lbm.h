@@ -247,8 +247,11 @@ lbm_status lbm_adjoint_seed_macros(lbm_ctx *ctx, const void *g_rho, const void *
  * receives dF/dgamma . g_force, or NULL.  Async. */
 lbm_status lbm_adjoint_seed_force(lbm_ctx *ctx, const double g_force[3], double *g_inlet, double *g_gain);
 
-/* Advance nsteps forward (as lbm_step), first copying the state before each
- * step into tape + k * lbm_state_bytes (device, caller-owned).  Async. */
+/* Advance nsteps forward (as lbm_step), leaving the state before step k in
+ * tape + k * lbm_state_bytes (device, caller-owned, nsteps slots).  When the
+ * tape and the slot size are 256-byte aligned, step k reads slot k and writes
+ * slot k + 1 directly (one state copy per call); otherwise each slot is copied
+ * before its step.  The results are the same bits either way.  Async. */
 lbm_status lbm_record_tape(lbm_ctx *ctx, int32_t nsteps, void *tape);
 
 /* Reverse sweep over a tape of nsteps forward states (as written by

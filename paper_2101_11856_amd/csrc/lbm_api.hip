@@ -418,13 +418,22 @@ lbm_status lbm_set_pose(lbm_ctx *c, const double R[9], const double o[3], const 
     return LBM_OK;
 }
 
+// one step from (fA, scA) into (fB, scB), without the swap
+static hipError_t one_step(lbm_ctx *c)
+{
+    if (c->nm > 0) {
+        const hipError_t e = launch_band_ib(c, c->fA, c->ftot);
+        if (e != hipSuccess) return e;
+    }
+    return launch_fused(c);
+}
+
 lbm_status lbm_step(lbm_ctx *c, int32_t nsteps)
 {
     CHECK_CTX(c);
     if (nsteps < 0) return fail(c, LBM_E_INVAL, "nsteps must be >= 0");
     for (int32_t t = 0; t < nsteps; ++t) {
-        if (c->nm > 0) HIP_TRY(c, launch_band_ib(c, c->fA, c->ftot), "lbm_step (immersed boundary)");
-        HIP_TRY(c, launch_fused(c), "lbm_step (fused)");
+        HIP_TRY(c, one_step(c), "lbm_step");
         std::swap(c->fA, c->fB);
         std::swap(c->scA, c->scB);
     }
@@ -537,13 +546,40 @@ lbm_status lbm_record_tape(lbm_ctx *c, int32_t nsteps, void *tape)
     CHECK_CTX(c);
     if (nsteps < 0) return fail(c, LBM_E_INVAL, "nsteps must be >= 0");
     if (nsteps > 0 && !tape) return fail(c, LBM_E_INVAL, "tape is NULL");
-    const size_t sb = state_bytes(c);
-    for (int32_t k = 0; k < nsteps; ++k) {
-        const lbm_status s = lbm_checkpoint(c, static_cast<char *>(tape) + (size_t)k * sb);
-        if (s != LBM_OK) return s;
-        const lbm_status t = lbm_step(c, 1);
-        if (t != LBM_OK) return t;
+    const size_t sb = state_bytes(c), fb = (size_t)c->g.total * c->esize;
+    char *t = static_cast<char *>(tape);
+    if (nsteps < 2 || reinterpret_cast<uintptr_t>(t) % ALIGN || sb % ALIGN || fb % ALIGN) {
+        for (int32_t k = 0; k < nsteps; ++k) {
+            const lbm_status s = lbm_checkpoint(c, t + (size_t)k * sb);
+            if (s != LBM_OK) return s;
+            const lbm_status u = lbm_step(c, 1);
+            if (u != LBM_OK) return u;
+        }
+        return LBM_OK;
     }
+    // Slot 0 is a copy of the state; step k then reads slot k and writes its
+    // result straight into slot k + 1 (the last step into the context's own
+    // buffer), so the tape costs one copy per call instead of one per step.
+    const lbm_status s0 = lbm_checkpoint(c, t);
+    if (s0 != LBM_OK) return s0;
+    void *ownA = c->fA, *ownB = c->fB;
+    float *ownSA = c->scA, *ownSB = c->scB;
+    auto slot_f = [&](int32_t k) { return static_cast<void *>(t + (size_t)k * sb); };
+    auto slot_s = [&](int32_t k) { return c->p.passive_scalar ? reinterpret_cast<float *>(t + (size_t)k * sb + fb) : nullptr; };
+    hipError_t e = hipSuccess;
+    for (int32_t k = 0; k < nsteps && e == hipSuccess; ++k) {
+        c->fA = k == 0 ? ownA : slot_f(k);
+        c->scA = k == 0 ? ownSA : slot_s(k);
+        c->fB = k == nsteps - 1 ? ownB : slot_f(k + 1);
+        c->scB = k == nsteps - 1 ? ownSB : slot_s(k + 1);
+        e = one_step(c);
+    }
+    // the context's buffers again; the final state is in ownB
+    c->fA = ownB;
+    c->fB = ownA;
+    c->scA = ownSB;
+    c->scB = ownSA;
+    if (e != hipSuccess) return hip_fail(c, e, "lbm_record_tape");
     return LBM_OK;
 }
 

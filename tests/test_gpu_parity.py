@@ -240,6 +240,37 @@ def test_checkpoint_restore_is_bitwise():
     assert torch.equal(a, b)
 
 
+def test_tape_equals_checkpoint_then_step():
+    """lbm_record_tape steps straight into the tape's slots (one copy per call):
+    every slot and the final state equal, bit for bit, a checkpoint taken
+    before each lbm_step(1), with samples and the passive scalar in the state."""
+    say("tape vs checkpoint + step")
+    nx, ny, nz = 70, 18, 16
+    xyz, ub, area, gain = _ib_scene(nx, ny, nz, 13)
+    rng = np.random.default_rng(14)
+    rho = (1.0 + 1e-3 * rng.standard_normal((nz, ny, nx))).astype(np.float32)
+    u = (0.01 * rng.standard_normal((3, nz, ny, nx))).astype(np.float32)
+    sc0 = rng.uniform(0.0, 1.0, (nz, ny, nx)).astype(np.float32)
+    runs = []
+    for taped in (False, True):
+        s = gpu_solver(nx, ny, nz, 0.05, faces=(IN, OUT, NS, FS, P, P), u_in=(0.03, 0, 0), scalar=True,
+                       scalar_inlet_height=6)
+        s.init_equilibrium(rho, u)
+        s.set_scalar(sc0)
+        s.set_solids(xyz, ub, area, gain)
+        k = 5
+        if taped:
+            slots = s.record_tape(k)
+        else:
+            slots = torch.empty((k, s.state_bytes()), dtype=torch.uint8, device="cuda")
+            for j in range(k):
+                s.checkpoint(slots[j])
+                s.step(1)
+        runs.append((slots.clone(), s.checkpoint().clone(), s.ib_force()))
+    (a, fa, Fa), (b, fb, Fb) = runs
+    assert torch.equal(a, b) and torch.equal(fa, fb) and np.array_equal(Fa, Fb)
+
+
 def test_nonfinite_state_reported():
     say("non-finite detection")
     from paper_2101_11856_amd import lbm
