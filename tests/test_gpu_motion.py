@@ -3,8 +3,8 @@ with re-sorting and re-banding (lbm_set_pose), and the FP64 total torque,
 against the oracle's rigid_pose + set_markers + step on the same kinematics.
 
 Gates: FP32 rel-L2 on rho and u <= 1e-5, force and torque <= 1e-4 (FP32
-per-sample forces summed in another order); FP64 to round-off; FP16 storage
-1e-3 (its velocity target) on the fields, force and torque; the sample
+per-sample forces summed in another order); FP64 to round-off; FP16 and BF16
+storage 1e-3 (the 16-bit velocity target) on the fields, force and torque; the sample
 maps after every placement bit-exact (both sides round the placed position
 to FP32 from the same FP64 operations).  The library keeps sample data in
 FP32 (the sample arrays of its interface), so the oracle is given the placed
@@ -57,7 +57,7 @@ def _flow(nx, ny, nz):
     return rho, u
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
 def test_moving_torus_matches_oracle(storage):
     nx, ny, nz = SHAPE
     steps = 12
@@ -70,8 +70,8 @@ def test_moving_torus_matches_oracle(storage):
     s = gpu_solver(nx, ny, nz, 0.05, storage=storage, faces=FACES)
     s.init_equilibrium(rho.astype(real), u.astype(real))
     s.set_body(X, ub, area, gain, *_pose(0))
-    # FP16 keeps d = f - w in 11 bits: fields, force and torque at its 1e-3 velocity target
-    fgate, tol = {"f64": (1e-11, 1e-12), "f32": (1e-4, 1e-5), "f16": (1e-3, 1e-3)}[storage]
+    # FP16 / BF16 keep d = f - w in 11 / 8 bits: fields, force and torque at the 1e-3 velocity target
+    fgate, tol = {"f64": (1e-11, 1e-12), "f32": (1e-4, 1e-5), "f16": (1e-3, 1e-3), "bf16": (1e-3, 1e-3)}[storage]
     worst_F = worst_T = 0.0
     for t in range(steps):
         R, o, v, w = _pose(t)
