@@ -169,7 +169,8 @@ def test_passive_scalar_many_steps():
     assert e_s <= 1e-5
 
 
-def test_city_full_size_maps_and_sampled_nodes():
+@pytest.mark.parametrize("storage,tol_f,tol_s", [("f32", 1e-6, 1e-6), ("f16", 1e-4, 1e-6)])
+def test_city_full_size_maps_and_sampled_nodes(storage, tol_f, tol_s):
     """City 1200x250x840 at full size (252M nodes, 3.86M samples), in the
     launch configuration the benchmark times.  The FP64 oracle cannot step the
     whole domain (its state is ~110 GB), so: (1) the integer maps are compared
@@ -180,15 +181,18 @@ def test_city_full_size_maps_and_sampled_nodes():
     method depends on a node's neighbourhood within 3 nodes (pull, the samples
     around the node, their stencils' pulls), so a box that keeps the real faces
     where it touches them and puts its own faces >= 5 nodes away gives the
-    node's exact result."""
-    say("city 1200x250x840 full size: maps bit-exact + one step at sampled nodes vs oracle boxes, fp32")
+    node's exact result.  FP16 storage rounds the deviations (up to ~0.05) to
+    11 bits, half an ulp being ~4e-5 of the largest population: gate 1e-4 on
+    populations; the scalar is FP32 in every storage form: gate 1e-6."""
+    say(f"city 1200x250x840 full size: maps bit-exact + one step at sampled nodes vs oracle boxes, {storage}")
     nx, ny, nz = 1200, 250, 840
     faces = (IN, OUT, NS, FS, P, P)
     h_sc = 50
     xyz, ub, area, gain = synth.city_markers(synth.city_boxes())
     n = xyz.shape[1]
     rho, u, sc0 = smooth_fields(nx, ny, nz)
-    s = gpu_solver(nx, ny, nz, 1e-5, faces=faces, u_in=(0.05, 0, 0), scalar=True, scalar_inlet_height=h_sc)
+    s = gpu_solver(nx, ny, nz, 1e-5, storage=storage, faces=faces, u_in=(0.05, 0, 0), scalar=True,
+                   scalar_inlet_height=h_sc)
     s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
     s.set_scalar(torch.from_numpy(sc0).cuda())
     s.set_solids(xyz, ub, area, gain)
@@ -239,5 +243,5 @@ def test_city_full_size_maps_and_sampled_nodes():
         e_f = float(np.abs(f_gpu[:, k] - f_ref).max() / np.abs(f_ref).max())
         e_s = abs(sc_gpu[k] - s_ref)
         worst_f, worst_s = max(worst_f, e_f), max(worst_s, e_s)
-        assert e_f <= 1e-6 and e_s <= 1e-6, (picks[k], e_f, e_s)
+        assert e_f <= tol_f and e_s <= tol_s, (picks[k], e_f, e_s)
     say(f"  {len(picks)} sampled nodes: max rel err populations {worst_f:.2e}, scalar {worst_s:.2e}")
