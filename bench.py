@@ -264,7 +264,7 @@ def main():
     ap.add_argument("--storage", default="f32", help="population storage of --profile-pass")
     ap.add_argument("--profile-pass", action="store_true",
                     help="profiler pass: the workload only, then 3 state copies of known size (calibration)")
-    ap.add_argument("--workload", default="turbulence", choices=["turbulence", "sphere", "city", "moving_torus"],
+    ap.add_argument("--workload", default="turbulence", choices=["turbulence", "sphere", "city", "moving_torus", "adjoint"],
                     help="workload of --profile-pass")
     args = ap.parse_args()
 
@@ -284,6 +284,9 @@ def main():
         return
     if args.profile_pass and args.workload == "moving_torus":
         print(json.dumps(moving_torus_workload(args.steps, args.warmup)), flush=True)
+        return
+    if args.profile_pass and args.workload == "adjoint":
+        print(json.dumps(adjoint_workload(args.steps, min(args.steps, 100))), flush=True)
         return
     if args.profile_pass and args.workload == "city":
         print(json.dumps(city_workload(args.steps, args.warmup, args.storage)), flush=True)
