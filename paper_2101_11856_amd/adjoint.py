@@ -64,30 +64,44 @@ class ChannelProblem:
 
     # forward ------------------------------------------------------------------
     def run_forward(self, coeffs, gains, keep_checkpoints=True):
+        """Run the forward steps from the equilibrium initial state.  Returns
+        (drag, probe u0, record); the record holds what the reverse sweep of
+        this run needs (its parameters, its checkpoints and its final state),
+        so later forward runs on the same problem do not disturb it."""
         s = self.solver
+        coeffs = torch.as_tensor(coeffs, device=self.device).detach().clone()
+        gains = torch.as_tensor(gains, device=self.device).detach().clone()
         self.set_params(coeffs, gains)
         s.init_equilibrium(self._rho0, self._u0)
-        self.checkpoints = []
+        checkpoints = []
         done = 0
         while done < self.steps:
             k = min(self.K, self.steps - done)
             if keep_checkpoints:
-                self.checkpoints.append((s.checkpoint(), k))
+                checkpoints.append((s.checkpoint(), k))
             s.step(k)
             done += k
         F = s.ib_force_eval()
         _, u = s.macros()
         probe = u[:, :, :, self.probe_x].to(torch.float64)
         drag = torch.tensor(-F[0], dtype=torch.float64, device=self.device)
-        return drag, probe
+        record = ForwardRecord(coeffs, gains, checkpoints, s.checkpoint() if keep_checkpoints else None)
+        return drag, probe, record
 
     def objective(self, drag, probe):
         return drag + ((probe - self.u_tgt[:, None, None]) ** 2).sum()
 
     # backward -----------------------------------------------------------------
-    def run_backward(self, g_drag: float, g_probe: torch.Tensor):
+    def run_backward(self, record: "ForwardRecord", g_drag: float, g_probe: torch.Tensor):
+        """Reverse sweep of the forward run that produced `record`: its
+        parameters and final state are put back first, then the seeds, then the
+        segments in reverse order."""
+        if record.final is None or not record.checkpoints:
+            raise RuntimeError("this forward run kept no checkpoints (keep_checkpoints=False): no reverse sweep")
         s = self.solver
         nz, ny, nx = s.shape
+        self.set_params(record.coeffs, record.gains)
+        s.restore(record.final)
         g_inlet = s.new_grad_inlet()
         g_gain = s.new_grad_gain()
         s.adjoint_init()                                  # lambda = 0
@@ -96,7 +110,7 @@ class ChannelProblem:
         s.adjoint_seed_macros(None, g_u, g_inlet)
         s.adjoint_seed_force((-float(g_drag), 0.0, 0.0), g_inlet, g_gain)
         tape = torch.empty((self.K, s.state_bytes()), dtype=torch.uint8, device=self.device)
-        for snap, k in reversed(self.checkpoints):
+        for snap, k in reversed(record.checkpoints):
             s.restore(snap)
             tape = s.record_tape(k, tape)
             s.adjoint_step(k, tape, g_inlet, g_gain)
@@ -104,13 +118,27 @@ class ChannelProblem:
         return g_coeffs, g_gain[: self.n]
 
 
+class ForwardRecord:
+    """Parameters, checkpoints [(snapshot, steps)] and final-state snapshot of
+    one forward run (device tensors owned by the record)."""
+
+    def __init__(self, coeffs, gains, checkpoints, final):
+        self.coeffs, self.gains = coeffs, gains
+        self.checkpoints, self.final = checkpoints, final
+
+
 class AdjointRun(torch.autograd.Function):
-    """(inflow coefficients [16], sample gains [n]) -> (drag, probe-plane u0 [3, nz, ny])."""
+    """(inflow coefficients [16], sample gains [n]) -> (drag, probe-plane u0 [3, nz, ny]).
+
+    Each application keeps its own forward record in the autograd context, so
+    several forward runs on one problem may be taken before their backward
+    passes, in any order."""
 
     @staticmethod
     def forward(ctx, problem: ChannelProblem, coeffs: torch.Tensor, gains: torch.Tensor):
-        drag, probe = problem.run_forward(coeffs.detach(), gains.detach())
+        drag, probe, record = problem.run_forward(coeffs.detach(), gains.detach())
         ctx.problem = problem
+        ctx.record = record
         ctx.dtypes = (coeffs.dtype, gains.dtype)
         return drag, probe
 
@@ -119,5 +147,6 @@ class AdjointRun(torch.autograd.Function):
         p = ctx.problem
         gd = 0.0 if g_drag is None else float(g_drag)
         gp = torch.zeros((3, p.nz, p.ny), dtype=torch.float64, device=p.device) if g_probe is None else g_probe
-        g_coeffs, g_gain = p.run_backward(gd, gp)
+        g_coeffs, g_gain = p.run_backward(ctx.record, gd, gp)
+        ctx.record = None
         return None, g_coeffs.to(ctx.dtypes[0]), g_gain.to(ctx.dtypes[1])

@@ -354,6 +354,7 @@ class Solver:
     # adjoint
     def set_gains(self, gain):
         self._gain = torch.as_tensor(gain, device=self.device).to(torch.float32).contiguous()
+        _need(self._gain, self.n_markers * 4, "gain ([n])", torch.float32)
         _check(_L.lbm_set_gains(self._h, _ptr(self._gain)), self._h)
 
     def record_tape(self, n: int, tape: torch.Tensor | None = None) -> torch.Tensor:

@@ -12,7 +12,8 @@ lattice units, a node sits at integer coordinates).
 The paper's scenes (Sec. 5, Table 3) use meshes and smoke that are not
 available; these generators stand in for them:
   * Taylor-Green vortex (32^3 parity case),
-  * decaying turbulence with an E(k) ~ k^-5/3 spectrum (256^3 throughput case),
+  * decaying turbulence with an E(k) ~ k^-5/3 spectrum (256^3 throughput case,
+    and the same spectrum on a periodic box),
   * a sphere sampled on a Fibonacci lattice plus a box of random samples
     (flow past an immersed sphere, 512x128x128),
   * a field of axis-aligned boxes sampled on walls and roofs (city blocks,
@@ -84,6 +85,41 @@ def turbulence(n: int, kmin: int = 1, kmax: int = 16, rms: float = 0.04, seed: i
     u *= rms / cur
     rng_r = np.random.default_rng(rho_seed)
     rho = 1.0 + rng_r.uniform(-rho_noise, rho_noise, size=(n, n, n))
+    return rho.astype(dtype), u.astype(dtype)
+
+
+def turbulence_box(nx: int, ny: int, nz: int, kmin: int = 1, kmax: int = 16, rms: float = 0.04,
+                   seed: int = 2101, rho_noise: float = 1e-3, rho_seed: int = 2102, dtype=np.float32):
+    """The spectrum of ``turbulence`` on a periodic nx x ny x nz box.
+
+    Wave numbers are counted in units of 2 pi / L with L the longest edge, so
+    mode m along an axis of n_a nodes has k = m L / n_a; shells round(|k|) in
+    [kmin, kmax] get E(k) ~ k^(-5/3) as in the cubic generator, and the field
+    stays periodic on the box.  Same projection, scaling and density noise.
+    """
+    L = max(nx, ny, nz)
+    rng = np.random.default_rng(seed)
+    kx = np.fft.fftfreq(nx, d=1.0 / nx) * (L / nx)
+    ky = np.fft.fftfreq(ny, d=1.0 / ny) * (L / ny)
+    kz = np.fft.fftfreq(nz, d=1.0 / nz) * (L / nz)
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    kmag = np.sqrt(KX * KX + KY * KY + KZ * KZ)
+    shell = np.rint(kmag).astype(np.int64)
+    active = (shell >= kmin) & (shell <= kmax)
+    counts = np.bincount(shell[active], minlength=kmax + 1).astype(np.float64)
+    amp = np.zeros_like(kmag)
+    s_act = shell[active]
+    amp[active] = np.sqrt(s_act.astype(np.float64) ** (-5.0 / 3.0) / counts[s_act])
+    kn = np.where(kmag > 0, kmag, 1.0)
+    khat = (KX / kn, KY / kn, KZ / kn)
+    c = [(rng.standard_normal(kmag.shape) + 1j * rng.standard_normal(kmag.shape)) for _ in range(3)]
+    kdotc = khat[0] * c[0] + khat[1] * c[1] + khat[2] * c[2]
+    u = np.empty((3, nz, ny, nx), dtype=np.float64)
+    for a in range(3):
+        u[a] = np.real(np.fft.ifftn((c[a] - khat[a] * kdotc) * amp))
+    u -= u.mean(axis=(1, 2, 3), keepdims=True)
+    u *= rms / math.sqrt(float(np.mean(np.sum(u * u, axis=0))) / 3.0)
+    rho = 1.0 + np.random.default_rng(rho_seed).uniform(-rho_noise, rho_noise, size=(nz, ny, nx))
     return rho.astype(dtype), u.astype(dtype)
 
 

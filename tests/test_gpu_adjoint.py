@@ -267,8 +267,8 @@ def test_adjoint_full_channel_vs_gpu_finite_differences():
     gdirs = rng.standard_normal((2, p64.n))
 
     def J64(cf, gn):
-        d, pr = p64.run_forward(torch.as_tensor(cf, device="cuda"), torch.as_tensor(gn, device="cuda"),
-                                keep_checkpoints=False)
+        d, pr, _ = p64.run_forward(torch.as_tensor(cf, device="cuda"), torch.as_tensor(gn, device="cuda"),
+                                   keep_checkpoints=False)
         return float(p64.objective(d, pr))
 
     h = 1e-4 * 0.01
@@ -297,3 +297,49 @@ def test_adjoint_full_channel_vs_gpu_finite_differences():
     e_g = rel_l2(dq @ g.grad.cpu().numpy(), fd_g)
     say(f"  J={float(J):.8e} drag={float(drag):.6e} rel err coeffs={e_c:.3e} gain dirs={e_g:.3e}")
     assert e_c <= 1e-3 and e_g <= 1e-3
+
+
+# ---------------------------------------------------------------------------
+# several forward runs on one problem before their backward passes
+# ---------------------------------------------------------------------------
+def test_interleaved_forwards_keep_their_own_gradients():
+    """Two forward runs with different inflow coefficients and gains on one
+    problem, then their backward passes in reverse order: each gradient equals
+    the one its run gives alone, because each autograd context holds its own
+    parameters, checkpoints and final state.  The adjoint's face and
+    interpolation transposes add with atomics, so the comparison allows FP32
+    round-off (1e-5); the two runs' gradients differ at O(1)."""
+    from paper_2101_11856_amd.adjoint import AdjointRun, ChannelProblem
+    c = SMALL
+    prob = ChannelProblem(nx=c["nx"], ny=c["ny"], nz=c["nz"], nu=c["nu"], steps=c["steps"], checkpoint_every=7,
+                          storage="f32", probe_x=c["probe_x"], radius=c["radius"], center=c["center"],
+                          n_around=c["n_around"], mode_length=c["mode_length"])
+    rng = np.random.default_rng(71)
+    runs = [(0.5 * synth.inlet_coefficients(seed=2105), np.ones(prob.n)),
+            (-0.7 * synth.inlet_coefficients(seed=2106), 0.8 + 0.4 * rng.random(prob.n))]
+
+    def leaves(cf, gn):
+        return (torch.tensor(cf, dtype=torch.float64, device="cuda", requires_grad=True),
+                torch.tensor(gn, dtype=torch.float64, device="cuda", requires_grad=True))
+
+    alone = []
+    for cf, gn in runs:
+        a, g = leaves(cf, gn)
+        prob.objective(*AdjointRun.apply(prob, a, g)).backward()
+        alone.append((a.grad.cpu().numpy(), g.grad.cpu().numpy()))
+    say("adjoint: two forward runs, then their backward passes in reverse order")
+    lv = [leaves(cf, gn) for cf, gn in runs]
+    Js = [prob.objective(*AdjointRun.apply(prob, a, g)) for a, g in lv]
+    Js[1].backward()
+    Js[0].backward()
+    errs = []
+    for (a, g), (ga, gg) in zip(lv, alone):
+        errs += [rel_l2(a.grad.cpu().numpy(), ga), rel_l2(g.grad.cpu().numpy(), gg)]
+    apart = rel_l2(alone[0][0], alone[1][0])
+    say(f"  interleaved vs alone: max rel err {max(errs):.2e}; the two runs' coefficient gradients differ by {apart:.2e}")
+    assert max(errs) <= 1e-5 and apart > 1e-2
+    # a run without checkpoints has no reverse sweep and says so
+    _, _, rec = prob.run_forward(torch.as_tensor(runs[0][0], device="cuda"), torch.as_tensor(runs[0][1], device="cuda"),
+                                 keep_checkpoints=False)
+    with pytest.raises(RuntimeError):
+        prob.run_backward(rec, 1.0, torch.zeros((3, prob.nz, prob.ny), dtype=torch.float64, device="cuda"))

@@ -34,7 +34,12 @@ def turb64_oracle():
     return rho, u, r, uu
 
 
-@pytest.mark.parametrize("storage,gate", [("f32", 1e-5), ("f16", 1e-3), ("bf16", None)])
+# Gates: FP32 1e-5 and FP16 1e-3 are the stated targets.  BF16 keeps an 8-bit
+# mantissa, and its round-to-nearest-even store error accumulates coherently
+# over the steps of a slowly changing field: measured 2.0e-3 here, so BF16
+# misses the 1e-3 target and is gated at its measured bound (3e-3), which
+# still catches any regression of a few tens of per cent.
+@pytest.mark.parametrize("storage,gate", [("f32", 1e-5), ("f16", 1e-3), ("bf16", 3e-3)])
 def test_storage_error_vs_oracle_turbulence64(turb64_oracle, storage, gate):
     rho, u, r_ref, u_ref = turb64_oracle
     say(f"turbulence 64^3 x 100 steps, storage={storage}")
@@ -44,11 +49,45 @@ def test_storage_error_vs_oracle_turbulence64(turb64_oracle, storage, gate):
     r, uu = (to_np(t) for t in s.macros())
     e_u, e_r = rel_l2(uu, u_ref), rel_l2(r, r_ref)
     say(f"  rel-L2 u={e_u:.3e} rho={e_r:.3e}")
-    if gate is not None:
-        assert e_u <= gate and e_r <= gate
-    else:
-        # BF16 (8-bit mantissa) is reported, not gated; it must still be a sane flow
-        assert np.isfinite(e_u) and e_u < 0.05
+    assert e_u <= gate and e_r <= gate
+
+
+# ---------------------------------------------------------------------------
+# the kernel the benchmark times, 100 steps against the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,walls", [((256, 32, 32), False), ((256, 24, 16), True)])
+def test_row_staged_fp32_100_steps_vs_oracle(shape, walls):
+    """FP32 storage with 256-node rows: the four 64-node segments of a row fill
+    one workgroup and x is periodic, which selects the LDS row-staged form of
+    the fused kernel (the form the 256^3 benchmark runs).  Rows off the y/z
+    faces take the staged pull, rows on no-slip y walls (second case, driven
+    by a body force) the face-aware pull inside the same kernel.  Input: the
+    k^-5/3 spectrum on the periodic box.  100 steps; rel-L2 and per-node
+    maximum error of rho and u against the FP64 oracle."""
+    nx, ny, nz = shape
+    faces = (P, P, NS, NS, P, P) if walls else (P,) * 6
+    body = (2e-6, 0.0, 0.0) if walls else (0.0, 0.0, 0.0)
+    rho, u = synth.turbulence_box(nx, ny, nz)
+    say(f"row-staged fp32 {nx}x{ny}x{nz}, walls={walls}, 100 steps")
+    s = gpu_solver(nx, ny, nz, 1e-4, faces=faces, body=body)
+    s.init_equilibrium(rho, u)
+    s.step(100)
+    r, uu = (to_np(t) for t in s.macros())
+    c = s.conserved()
+    del s
+    S = O.OracleSim(nx, ny, nz, 1e-4, faces=faces, body=body)
+    S.init_equilibrium(rho.astype(np.float64), u.astype(np.float64))
+    S.step(100)
+    r_ref, u_ref = S.macros()
+    c_ref = S.conserved()
+    S.close()
+    e_u, e_r = rel_l2(uu, u_ref), rel_l2(r, r_ref)
+    m_u = float(np.abs(uu - u_ref).max() / np.abs(u_ref).max())
+    m_r = float(np.abs(r - r_ref).max())
+    say(f"  rel-L2 u={e_u:.3e} rho={e_r:.3e}; max |du|/max|u|={m_u:.3e}, max |drho|={m_r:.3e}")
+    assert e_u <= 1e-5 and e_r <= 1e-5
+    assert m_u <= 1e-5 and m_r <= 1e-5
+    assert abs(c[0] - c_ref[0]) <= 1e-6 * c_ref[0]
 
 
 # ---------------------------------------------------------------------------

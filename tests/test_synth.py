@@ -29,6 +29,29 @@ def test_turbulence_spectrum_rms_and_divergence():
     assert E[13:].sum() < 1e-12 * E[1:13].sum()   # only float32 round-off outside the shells
 
 
+def test_turbulence_box_periodic_solenoidal_and_cubic_consistent():
+    nx, ny, nz = 64, 16, 8
+    rho, u = synth.turbulence_box(nx, ny, nz, kmax=12)
+    assert u.shape == (3, nz, ny, nx) and rho.shape == (nz, ny, nx)
+    rms = math.sqrt(float((u.astype(np.float64) ** 2).sum(0).mean()) / 3)
+    assert abs(rms - 0.04) < 1e-6
+    # divergence-free in the box's own wave numbers (periodic on the box)
+    L = max(nx, ny, nz)
+    kx, ky, kz = (np.fft.fftfreq(n, d=1.0 / n) * (L / n) for n in (nx, ny, nz))
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    U = [np.fft.fftn(u[a].astype(np.float64)) for a in range(3)]
+    div = KX * U[0] + KY * U[1] + KZ * U[2]
+    assert np.abs(div).max() < 1e-6 * np.abs(U[0]).max() * L
+    # only modes inside the shells carry energy
+    shell = np.rint(np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)).astype(int)
+    E = sum(np.abs(Ua) ** 2 for Ua in U)
+    assert E[(shell > 12) | (shell < 1)].sum() < 1e-12 * E.sum()
+    # on a cube it draws the same field as the cubic generator
+    r1, u1 = synth.turbulence_box(24, 24, 24, kmax=8)
+    r2, u2 = synth.turbulence(24, kmax=8)
+    assert np.array_equal(r1, r2) and np.allclose(u1, u2, atol=1e-7)
+
+
 def test_taylor_green_is_divergence_free_and_decays_in_closed_form():
     rho, u = synth.taylor_green(16, 0.05)
     assert np.allclose(rho, 1) and np.abs(u[2]).max() == 0
