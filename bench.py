@@ -29,7 +29,8 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "k_fused_turbulence256_f32_counters.txt")
 # sources that decide the fused kernel's code and memory layout, the calibration copy, and the build flags
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2101_11856_amd", "csrc", f)
-                  for f in ("lbm_step.hip", "lbm_internal.hpp", "lbm_api.hip", "lbm_ctx.hpp", "lbm_aux.hip")]
+                  for f in ("lbm_step.hip", "lbm_step.hpp", "lbm_step_inst.hip", "lbm_internal.hpp", "lbm_api.hip",
+                            "lbm_ctx.hpp", "lbm_aux.hip")]
 KERNEL_SOURCES.append(os.path.join(ROOT, "paper_2101_11856_amd", "build.py"))
 
 

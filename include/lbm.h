@@ -71,6 +71,18 @@ typedef enum { LBM_PERIODIC = 0, LBM_NOSLIP = 1, LBM_FREESLIP = 2, LBM_INLET = 3
  * (FP64 storage and arithmetic).  16-bit forms round to nearest even. */
 typedef enum { LBM_F32 = 0, LBM_F16DEV = 1, LBM_BF16DEV = 2, LBM_F64 = 3 } lbm_storage;
 
+/* Collision model of the fused step.  LBM_CM is the paper's central-moment
+ * MRT (Sec. 3, Eqs. 4-5).  LBM_BGK and LBM_RMMRT are the comparison models of
+ * its Sec. 5.1 (collision-cost figure), which the paper names but does not
+ * print; readings: both use the same product-form equilibrium, half-force
+ * velocity u = (j + F/2)/rho and Guo forcing as LBM_CM.  LBM_BGK relaxes every
+ * population at the one rate s_nu (s_bulk and s_high unused):
+ *     f' = f - s_nu (f - f_eq(rho, u)) + (1 - s_nu/2) F . dPhi/du,
+ * f_eq = rho Phi(u).  LBM_RMMRT relaxes the moments of the central-moment
+ * model's combination basis taken about zero velocity (raw moments) at the
+ * same per-group rates.  With all rates equal the three coincide. */
+typedef enum { LBM_CM = 0, LBM_BGK = 1, LBM_RMMRT = 2 } lbm_collision;
+
 typedef struct {
     int32_t nx, ny, nz;          /* nodes per axis (>= 1; >= 2 on an axis with a non-periodic face) */
     double nu;                   /* lattice kinematic viscosity > 0; shear rate s_nu = 1/(3 nu + 1/2) (Sec. 3) */
@@ -83,9 +95,11 @@ typedef struct {
     int32_t storage;             /* lbm_storage */
     int32_t passive_scalar;      /* 0/1: advect a passive scalar (first-order upwind) */
     int32_t scalar_inlet_height; /* scalar held at 1 on inlet nodes with y < this height */
+    int32_t collision;           /* lbm_collision (default LBM_CM) */
 } lbm_params;
 
-/* Fill *p with defaults: periodic faces, s_bulk = s_high = 1, FP32, no scalar. */
+/* Fill *p with defaults: periodic faces, s_bulk = s_high = 1, FP32, no scalar,
+ * central-moment collision. */
 lbm_status lbm_default_params(lbm_params *p, int32_t nx, int32_t ny, int32_t nz, double nu);
 
 /* Device bytes the caller must provide to lbm_create for these parameters. */
@@ -101,8 +115,11 @@ lbm_status lbm_workspace_size(const lbm_params *p, size_t *bytes);
  * the largest power of two with at most 2048 padded nodes per block),
  * LBM_POINTER_PATH = 1 stores through plain pointers instead of per-row buffer
  * descriptors, LBM_ROW_STAGE = 0 / 1 disables / forces LDS row staging of the
- * pull (default: FP32 rows that fill one workgroup with periodic x).  Keep
- * them unchanged between the two calls. */
+ * pull (default: FP32 rows that fill one workgroup with periodic x),
+ * LBM_CM_GENERAL = 1 keeps the general central-moment collision when the
+ * orders 3 to 6 have unit rates (by default a form specialised to unit rates
+ * runs, which needs the forward transform only up to order 2).  Keep them
+ * unchanged between the two calls. */
 lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out);
 
 lbm_status lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
@@ -233,7 +250,9 @@ lbm_status lbm_set_gains(lbm_ctx *ctx, const float *gain);
 lbm_status lbm_adjoint_ws_size(const lbm_ctx *ctx, size_t *bytes);
 
 /* Bind the adjoint workspace (device, 256-byte aligned) and set lambda = 0.
- * Must be called again after lbm_set_solids or lbm_set_pose.  Async. */
+ * Must be called again after lbm_set_solids or lbm_set_pose.  The adjoint
+ * differentiates the central-moment collision: a context with another
+ * collision model returns LBM_E_UNSUPPORTED.  Async. */
 lbm_status lbm_adjoint_init(lbm_ctx *ctx, void *adj_ws, size_t bytes);
 
 /* lambda += (d(rho, u0)/df)^T (g_rho, g_u) for the lbm_macros outputs of the

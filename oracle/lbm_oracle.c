@@ -51,6 +51,14 @@
  *     base cell b = floor(x_s) taken in FP32, rho at the sample interpolated
  *     with the same kernel, per-sample gain gamma_s and area a_s
  *     (g_s = gamma_s rho_s (u_b - u_s), spread a_s K g_s).
+ *   - comparison collision models (Sec. 5.1, the collision-cost figure): the
+ *     paper compares D3Q27 BGK and raw-moment MRT (RM-MRT) with its model but
+ *     prints neither; both are taken with the same product-form equilibrium,
+ *     half-force velocity and Guo forcing as the central-moment model, so the
+ *     three differ only in the space where relaxation happens.  BGK relaxes
+ *     every population at one rate omega = s_nu; RM-MRT relaxes the moments
+ *     of the same combination basis C taken about zero velocity, M0 = C T(0),
+ *     at the same per-group rates.
  *   - faces: no-slip = halfway bounce-back (Alg. 1); inlet = bounce-back with
  *     a wall velocity term 2 w_i rho_w (c_i.u_in)/cs^2, rho_w = 1; outflow =
  *     copy of the streamed value one node inward; free-slip = specular
@@ -346,6 +354,85 @@ int orc_collide(const double *fs, const double F[3], double s_nu, double s_b, co
 }
 
 /* ------------------------------------------------------------------------ */
+/* Comparison collision models (Sec. 5.1): BGK and raw-moment MRT            */
+/* ------------------------------------------------------------------------ */
+
+/* Guo forcing shape of the product-form equilibrium: G_i = sum_a F_a
+ * d Phi_i / d u_a with Phi_i(u) = prod_a phi_{c_ia}(u_a) (so f_eq = rho Phi),
+ * phi_0 = 2/3 - u^2 (derivative -2u), phi_{+-1} = (1/3 +- u + u^2)/2
+ * (derivative (+-1 + 2u)/2). */
+void orc_forcing_shape(const double u[3], const double F[3], double *G)
+{
+    for (int i = 0; i < Q; ++i) {
+        double phi[3], dphi[3];
+        for (int a = 0; a < 3; ++a) {
+            const double ua = u[a];
+            if (CV[i][a] == 0) {
+                phi[a] = 2.0 / 3.0 - ua * ua;
+                dphi[a] = -2.0 * ua;
+            } else {
+                phi[a] = (1.0 / 3.0 + CV[i][a] * ua + ua * ua) * 0.5;
+                dphi[a] = (CV[i][a] + 2.0 * ua) * 0.5;
+            }
+        }
+        G[i] = F[0] * dphi[0] * phi[1] * phi[2] + F[1] * phi[0] * dphi[1] * phi[2] + F[2] * phi[0] * phi[1] * dphi[2];
+    }
+}
+
+/* density, momentum and half-force velocity of pulled populations */
+static double half_force_velocity(const double *fs, const double F[3], double u[3])
+{
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        rho += fs[i];
+        for (int a = 0; a < 3; ++a) j[a] += CV[i][a] * fs[i];
+    }
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + F[a] / 2.0) / rho;
+    return rho;
+}
+
+/* Lattice BGK: one relaxation rate for every population,
+ * fpost = fs - omega (fs - f_eq(rho, u)) + (1 - omega/2) G. */
+int orc_collide_bgk(const double *fs, const double F[3], double omega, double *fpost)
+{
+    double u[3], feq[Q], G[Q];
+    const double rho = half_force_velocity(fs, F, u);
+    orc_equilibrium(rho, u, feq);
+    orc_forcing_shape(u, F, G);
+    for (int i = 0; i < Q; ++i) fpost[i] = fs[i] - omega * (fs[i] - feq[i]) + (1.0 - 0.5 * omega) * G[i];
+    return 0;
+}
+
+/* Raw-moment MRT in the basis M0 = C T(0): m = M0 fs, m_eq = M0 f_eq(rho, u),
+ * m_F = M0 G; m' = m - D (m - m_eq) + (I - D/2) m_F with the per-group rates
+ * of the central-moment model; fpost solves M0 fpost = m'. */
+int orc_collide_rm(const double *fs, const double F[3], double s_nu, double s_b, const double s_high[4],
+                   double *fpost)
+{
+    double u[3], feq[Q], G[Q];
+    const double rho = half_force_velocity(fs, F, u);
+    orc_equilibrium(rho, u, feq);
+    orc_forcing_shape(u, F, G);
+    const double zero[3] = {0.0, 0.0, 0.0};
+    double M0[Q * Q];
+    orc_basis_matrix(zero, M0);
+    double mp[Q];
+    for (int k = 0; k < Q; ++k) {
+        double m = 0.0, me = 0.0, mf = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            m += M0[k * Q + i] * fs[i];
+            me += M0[k * Q + i] * feq[i];
+            mf += M0[k * Q + i] * G[i];
+        }
+        const double s = rate_of(k, s_nu, s_b, s_high);
+        mp[k] = m - s * (m - me) + (1.0 - 0.5 * s) * mf;
+    }
+    const int rc = gauss_solve(M0, mp, Q);
+    for (int i = 0; i < Q; ++i) fpost[i] = mp[i];
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Simulation state                                                          */
 /* ------------------------------------------------------------------------ */
 
@@ -368,6 +455,8 @@ typedef struct {
     int64_t *bucket;
     double *Gs;          /* [3][nm] last penalty forces */
     double ftot[3];
+    /* collision model: 0 central-moment MRT, 1 BGK, 2 raw-moment MRT */
+    int model;
     /* passive scalar (optional) */
     int scalar, scalar_inlet_height;
     double *sc, *sc2;
@@ -439,6 +528,15 @@ void orc_destroy(orc_sim *S)
 }
 
 int64_t orc_num_cells(const orc_sim *S) { return S->N; }
+
+/* collision model of the steps: 0 central-moment MRT (default), 1 BGK at
+ * rate s_nu, 2 raw-moment MRT; returns -1 for an unknown code */
+int orc_set_model(orc_sim *S, int model)
+{
+    if (model < 0 || model > 2) return -1;
+    S->model = model;
+    return 0;
+}
 
 void orc_set_state(orc_sim *S, const double *f) { memcpy(S->f, f, sizeof(double) * Q * S->N); }
 void orc_get_state(const orc_sim *S, double *f) { memcpy(f, S->f, sizeof(double) * Q * S->N); }
@@ -766,7 +864,11 @@ static int collide_all(orc_sim *S)
         double fs[Q], fp[Q], F[3];
         for (int i = 0; i < Q; ++i) fs[i] = S->fs[i * N + k];
         for (int a = 0; a < 3; ++a) F[a] = S->g[a * N + k] + S->body[a];
-        if (orc_collide(fs, F, S->s_nu, S->s_b, S->s_high, fp) != 0) bad = 1;
+        int rc;
+        if (S->model == 1) rc = orc_collide_bgk(fs, F, S->s_nu, fp);
+        else if (S->model == 2) rc = orc_collide_rm(fs, F, S->s_nu, S->s_b, S->s_high, fp);
+        else rc = orc_collide(fs, F, S->s_nu, S->s_b, S->s_high, fp);
+        if (rc != 0) bad = 1;
         for (int i = 0; i < Q; ++i) S->f[i * N + k] = fp[i];
     }
     return bad ? -1 : 0;

@@ -59,6 +59,13 @@ def lib():
         L.orc_equilibrium.argtypes = [C.c_double, dp, dp]
         L.orc_collide.argtypes = [dp, dp, C.c_double, C.c_double, dp, dp]
         L.orc_collide.restype = C.c_int
+        L.orc_collide_bgk.argtypes = [dp, dp, C.c_double, dp]
+        L.orc_collide_bgk.restype = C.c_int
+        L.orc_collide_rm.argtypes = [dp, dp, C.c_double, C.c_double, dp, dp]
+        L.orc_collide_rm.restype = C.c_int
+        L.orc_forcing_shape.argtypes = [dp, dp, dp]
+        L.orc_set_model.argtypes = [vp, C.c_int]
+        L.orc_set_model.restype = C.c_int
         L.orc_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, ip, dp, C.c_double, dp, dp, C.c_int]
         L.orc_create.restype = vp
         L.orc_destroy.argtypes = [vp]
@@ -160,6 +167,36 @@ def collide(fs, F=(0.0, 0.0, 0.0), s_nu=1.0, s_b=1.0, s_high=(1.0, 1.0, 1.0, 1.0
     return out
 
 
+def collide_bgk(fs, F=(0.0, 0.0, 0.0), omega=1.0) -> np.ndarray:
+    """Lattice BGK with the product-form equilibrium and Guo forcing (the
+    paper's Sec. 5.1 comparison model; reading: same equilibrium and forcing as
+    the central-moment model)."""
+    out = np.zeros(27)
+    lib().orc_collide_bgk(_p(_d(fs), C.c_double), _p(_d(F), C.c_double), float(omega), _p(out, C.c_double))
+    return out
+
+
+def collide_rm(fs, F=(0.0, 0.0, 0.0), s_nu=1.0, s_b=1.0, s_high=(1.0, 1.0, 1.0, 1.0)) -> np.ndarray:
+    """Raw-moment MRT: the same combination basis and rates, moments taken
+    about zero velocity (the paper's Sec. 5.1 comparison model)."""
+    out = np.zeros(27)
+    rc = lib().orc_collide_rm(_p(_d(fs), C.c_double), _p(_d(F), C.c_double), float(s_nu), float(s_b),
+                              _p(_d(s_high), C.c_double), _p(out, C.c_double))
+    if rc != 0:
+        raise np.linalg.LinAlgError("singular moment matrix")
+    return out
+
+
+def forcing_shape(u, F) -> np.ndarray:
+    """G_i = sum_a F_a d Phi_i / d u_a of the product-form equilibrium Phi."""
+    out = np.zeros(27)
+    lib().orc_forcing_shape(_p(_d(u), C.c_double), _p(_d(F), C.c_double), _p(out, C.c_double))
+    return out
+
+
+MODELS = {"cm": 0, "bgk": 1, "rm": 2}
+
+
 def rigid_pose(X, ub, R, o, v, w):
     """Sample update of Alg. 2 (c) for a rigid body in prescribed motion.
 
@@ -208,7 +245,7 @@ class OracleSim:
     """
 
     def __init__(self, nx, ny, nz, nu, faces=(0,) * 6, u_in=(0.0, 0.0, 0.0), s_bulk=1.0,
-                 s_high=(1.0, 1.0, 1.0, 1.0), body=(0.0, 0.0, 0.0), scalar=False):
+                 s_high=(1.0, 1.0, 1.0, 1.0), body=(0.0, 0.0, 0.0), scalar=False, model="cm"):
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
         fc = np.ascontiguousarray(np.asarray(faces, dtype=np.int32))
@@ -217,6 +254,8 @@ class OracleSim:
                                    1 if scalar else 0)
         if not self._h:
             raise ValueError("invalid oracle parameters")
+        if lib().orc_set_model(self._h, MODELS[model] if isinstance(model, str) else int(model)) != 0:
+            raise ValueError(f"unknown collision model {model!r}")
         self.n_markers = 0
 
     def close(self):

@@ -14,6 +14,13 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ["lbm_step.hip", "lbm_aux.hip", "lbm_adjoint.hip", "lbm_api.hip"]
+# the fused-step kernels, one object per (storage form, collision model), so
+# that the variants compile in parallel: (source, object, defines)
+STORAGES = {"f32": "LBM_F32", "f16": "LBM_F16DEV", "bf16": "LBM_BF16DEV", "f64": "LBM_F64"}
+COLLS = {"cm": 0, "cm1": 1, "bgk": 2, "rm": 3}
+UNITS = [("lbm_step_inst.hip", f"lbm_step_{st}_{cn}.o", (f"LBM_STEP_ST={sv}", f"LBM_STEP_COLL={cv}"))
+         for st, sv in STORAGES.items() for cn, cv in COLLS.items()]
+UNITS += [(src, src.replace(".hip", ".o"), ()) for src in SOURCES]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -25,8 +32,8 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, build_dir: str = BUILD, defines=()) -> str:
-    obj = os.path.join(build_dir, src.replace(".hip", ".o"))
+def _compile(src: str, build_dir: str = BUILD, defines=(), obj_name: str | None = None) -> str:
+    obj = os.path.join(build_dir, obj_name or src.replace(".hip", ".o"))
     cmd = ["hipcc", *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -38,8 +45,8 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     """Compile the sources (optionally with extra -D tuning switches) into `out`."""
     build_dir = BUILD if out == LIB else os.path.join(os.path.dirname(os.path.abspath(out)), "_build")
     os.makedirs(build_dir, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, build_dir, defines), SOURCES))
+    with cf.ThreadPoolExecutor(max_workers=min(len(UNITS), max(1, os.cpu_count() or 1), 16)) as ex:
+        objs = list(ex.map(lambda u: _compile(u[0], build_dir, (*defines, *u[2]), u[1]), UNITS))
     tmp = out + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

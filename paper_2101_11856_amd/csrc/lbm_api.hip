@@ -78,6 +78,7 @@ lbm_status validate(const lbm_params *p, std::string &err)
             return err = "u_in and body_force must be finite", LBM_E_INVAL;
     if (p->storage < LBM_F32 || p->storage > LBM_F64) return err = "unknown storage", LBM_E_INVAL;
     if (p->passive_scalar != 0 && p->passive_scalar != 1) return err = "passive_scalar must be 0 or 1", LBM_E_INVAL;
+    if (p->collision < LBM_CM || p->collision > LBM_RMMRT) return err = "unknown collision model", LBM_E_INVAL;
     return LBM_OK;
 }
 
@@ -232,6 +233,16 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, voi
         const long rs = r ? std::strtol(r, nullptr, 10) : -1;
         c->row_stage = rs != 0 && L.ntx == WAVES_PER_BLOCK && p->face[0] == LBM_PERIODIC &&
                        (p->storage == LBM_F32 || rs == 1);
+        // collision variant: the central-moment form specialised to unit
+        // rates of orders 3 to 6 when they are (LBM_CM_GENERAL=1 keeps the
+        // general form, for measurements)
+        const char *g = std::getenv("LBM_CM_GENERAL");
+        const bool general = g && std::strtol(g, nullptr, 10) != 0;
+        const bool unit_high = p->s_high[0] == 1.0 && p->s_high[1] == 1.0 && p->s_high[2] == 1.0 && p->s_high[3] == 1.0;
+        c->coll = p->collision == LBM_BGK     ? COLL_BGK
+                  : p->collision == LBM_RMMRT ? COLL_RM
+                  : (unit_high && !general)   ? COLL_CM_UNIT_HIGH
+                                              : COLL_CM;
     }
     c->ws = static_cast<char *>(workspace);
     c->ws_bytes = ws_bytes;
@@ -593,6 +604,8 @@ lbm_status lbm_adjoint_ws_size(const lbm_ctx *c, size_t *bytes)
 lbm_status lbm_adjoint_init(lbm_ctx *c, void *adj_ws, size_t bytes)
 {
     CHECK_CTX(c);
+    if (c->p.collision != LBM_CM)
+        return fail(c, LBM_E_UNSUPPORTED, "the adjoint differentiates the central-moment collision only");
     if (!adj_ws || reinterpret_cast<uintptr_t>(adj_ws) % ALIGN)
         return fail(c, LBM_E_INVAL, "adjoint workspace must be non-NULL and 256-byte aligned");
     if (bytes < adjoint_ws_bytes(c))

@@ -21,6 +21,7 @@ struct lbm_ctx {
     size_t rsize = 4;      // bytes of the arithmetic type
     bool buffer_path = false;  // fused kernel stores through per-row buffer descriptors
     bool row_stage = false;    // fused kernel stages whole rows in LDS (segments per row == waves per block, periodic x)
+    int coll = 0;              // collision variant of the fused kernel (COLL_* of lbm_internal.hpp)
     // caller workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;

@@ -616,6 +616,19 @@ __host__ __device__ __forceinline__ void velocity(const R (&m)[3][3][3], R Fx, R
     uz = (m[1][0][0] + (R)0.5 * Fz) * inv;
 }
 
+// Inverse path shared by the central-moment forms: central moments of d about
+// u -> raw moments -> populations (deviations).
+template <typename R> __host__ __device__ __forceinline__ void central_to_populations(R (&f)[3][3][3], R ux, R uy, R uz)
+{
+    lines_z(f, [uz](R &a, R &b, R &c) { unshift3(a, b, c, uz); });
+    lines_y(f, [uy](R &a, R &b, R &c) { unshift3(a, b, c, uy); });
+    lines_x(f, [ux](R &a, R &b, R &c) { unshift3(a, b, c, ux); });
+    auto iraw = [](R &a, R &b, R &c) { iraw3(a, b, c); };
+    lines_z(f, iraw);
+    lines_y(f, iraw);
+    lines_x(f, iraw);
+}
+
 // f holds the pulled deviations; on return f holds the post-collision
 // deviations and (rho, u) the density and half-force velocity used.
 template <typename R>
@@ -635,13 +648,302 @@ __host__ __device__ __forceinline__ void collide(R (&f)[3][3][3], R Fx, R Fy, R 
     lines_z(f, [uz](R &a, R &b, R &c) { shift3(a, b, c, uz); });
     relax(f, ux, uy, uz, drho, Fx, Fy, Fz, rt);
     // back to raw moments, then to populations
-    lines_z(f, [uz](R &a, R &b, R &c) { unshift3(a, b, c, uz); });
-    lines_y(f, [uy](R &a, R &b, R &c) { unshift3(a, b, c, uy); });
-    lines_x(f, [ux](R &a, R &b, R &c) { unshift3(a, b, c, ux); });
+    central_to_populations(f, ux, uy, uz);
+}
+
+// Raw moments of d up to second order (exponents (a,b,c) with a+b+c <= 2),
+// taken separably: x-pass on all 9 lines, then only the y and z sums that
+// feed a moment of order <= 2 (66 additions instead of the 81 of the full
+// transform).  m[c][b][a] = sum d c_x^a c_y^b c_z^c.
+template <typename R> struct Low {
+    R m000, m100, m010, m001, m200, m020, m002, m110, m101, m011;
+};
+template <typename R> __host__ __device__ __forceinline__ Low<R> low_moments(const R (&f)[3][3][3])
+{
+    R X0[3][3], X1[3][3], X2[3][3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+            const R s = f[z][y][2] + f[z][y][0];
+            X1[z][y] = f[z][y][2] - f[z][y][0];
+            X0[z][y] = s + f[z][y][1];
+            X2[z][y] = s;
+        }
+    R Y00[3], Y01[3], Y02[3], Y10[3], Y11[3], Y20[3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z) {
+        const R s0 = X0[z][2] + X0[z][0];
+        Y00[z] = s0 + X0[z][1];
+        Y01[z] = X0[z][2] - X0[z][0];
+        Y02[z] = s0;
+        Y10[z] = (X1[z][2] + X1[z][0]) + X1[z][1];
+        Y11[z] = X1[z][2] - X1[z][0];
+        Y20[z] = (X2[z][2] + X2[z][0]) + X2[z][1];
+    }
+    Low<R> L;
+    const R s00 = Y00[2] + Y00[0];
+    L.m000 = s00 + Y00[1];
+    L.m001 = Y00[2] - Y00[0];
+    L.m002 = s00;
+    L.m010 = (Y01[2] + Y01[0]) + Y01[1];
+    L.m011 = Y01[2] - Y01[0];
+    L.m020 = (Y02[2] + Y02[0]) + Y02[1];
+    L.m100 = (Y10[2] + Y10[0]) + Y10[1];
+    L.m101 = Y10[2] - Y10[0];
+    L.m110 = (Y11[2] + Y11[0]) + Y11[1];
+    L.m200 = (Y20[2] + Y20[0]) + Y20[1];
+    return L;
+}
+
+// collide() for unit rates of orders 3 to 6 (the default): those central
+// moments relax fully, kappa' = kappa_eq + kappa_F / 2, so they depend on
+// rho, u and F only and the forward transform is needed up to order 2.  Same
+// post-collision state as collide() up to rounding.
+template <typename R>
+__host__ __device__ __forceinline__ void collide_unit_high(R (&f)[3][3][3], R Fx, R Fy, R Fz, const Rates<R> &rt,
+                                                           R &rho_o, R &ux_o, R &uy_o, R &uz_o)
+{
+    const Low<R> L = low_moments(f);
+    const R drho = L.m000;
+    const R inv = (R)1 / ((R)1 + drho);
+    const R ux = (L.m100 + (R)0.5 * Fx) * inv, uy = (L.m010 + (R)0.5 * Fy) * inv, uz = (L.m001 + (R)0.5 * Fz) * inv;
+    rho_o = (R)1 + drho;
+    ux_o = ux;
+    uy_o = uy;
+    uz_o = uz;
+    // central moments of d about u, orders 1 and 2
+    const R k100 = L.m100 - ux * drho, k010 = L.m010 - uy * drho, k001 = L.m001 - uz * drho;
+    const R k200 = L.m200 - ux * (L.m100 + k100);
+    const R k020 = L.m020 - uy * (L.m010 + k010);
+    const R k002 = L.m002 - uz * (L.m001 + k001);
+    const R k110 = L.m110 - ux * L.m010 - uy * k100;
+    const R k101 = L.m101 - ux * L.m001 - uz * k100;
+    const R k011 = L.m011 - uy * L.m001 - uz * k010;
+    const R third = (R)(1.0 / 3.0), ninth = (R)(1.0 / 9.0), t27 = (R)(1.0 / 27.0);
+    const R x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
+    const R px = third + x2, py = third + y2, pz = third + z2;
+    const R dr3 = drho * third, dr9 = drho * ninth;
+    // orders 0 and 1 (force added to the momentum)
+    f[0][0][0] = drho;
+    f[0][0][1] = k100 + Fx;
+    f[0][1][0] = k010 + Fy;
+    f[1][0][0] = k001 + Fz;
+    // order 2 as in relax(): shear rate on the off-diagonal and deviatoric
+    // parts, bulk rate on the trace
+    f[0][1][1] = k110 - rt.s_nu * (k110 + ux * uy);
+    f[1][0][1] = k101 - rt.s_nu * (k101 + ux * uz);
+    f[1][1][0] = k011 - rt.s_nu * (k011 + uy * uz);
+    {
+        const R nxx = k200 + x2 - dr3, nyy = k020 + y2 - dr3, nzz = k002 + z2 - dr3;
+        const R tr = (rt.s_b - rt.s_nu) * third * (nxx + nyy + nzz);
+        f[0][0][2] = k200 - (rt.s_nu * nxx + tr);
+        f[0][2][0] = k020 - (rt.s_nu * nyy + tr);
+        f[2][0][0] = k002 - (rt.s_nu * nzz + tr);
+    }
+    // orders 3 to 6 at rate 1: -Delta (the equilibrium in deviation form) plus
+    // half the force moments (F cs^2 on the (1,2,0) family, F cs^4 on (1,2,2))
+    const R f3 = (R)(1.0 / 6.0), f5 = (R)(1.0 / 18.0);
+    f[0][2][1] = ux * py + f3 * Fx;  // (1,2,0)
+    f[2][0][1] = ux * pz + f3 * Fx;  // (1,0,2)
+    f[0][1][2] = uy * px + f3 * Fy;  // (2,1,0)
+    f[2][1][0] = uy * pz + f3 * Fy;  // (0,1,2)
+    f[1][0][2] = uz * px + f3 * Fz;  // (2,0,1)
+    f[1][2][0] = uz * py + f3 * Fz;  // (0,2,1)
+    f[1][1][1] = ux * uy * uz;       // (1,1,1)
+    f[0][2][2] = dr9 - ((x2 + y2) * third + x2 * y2);  // (2,2,0)
+    f[2][0][2] = dr9 - ((x2 + z2) * third + x2 * z2);  // (2,0,2)
+    f[2][2][0] = dr9 - ((y2 + z2) * third + y2 * z2);  // (0,2,2)
+    f[1][1][2] = -(px * uy * uz);                      // (2,1,1)
+    f[1][2][1] = -(py * ux * uz);                      // (1,2,1)
+    f[2][1][1] = -(pz * ux * uy);                      // (1,1,2)
+    f[2][2][1] = ux * py * pz + f5 * Fx;               // (1,2,2)
+    f[2][1][2] = uy * px * pz + f5 * Fy;               // (2,1,2)
+    f[1][2][2] = uz * px * py + f5 * Fz;               // (2,2,1)
+    f[2][2][2] = drho * t27 - ((x2 * y2 + x2 * z2 + y2 * z2) * third + (x2 + y2 + z2) * ninth + x2 * y2 * z2);
+    central_to_populations(f, ux, uy, uz);
+}
+
+// ---------------------------------------------------------------------------
+// comparison collision models (Sec. 5.1 and its collision-cost figure): the
+// paper prints neither; both take the product-form equilibrium, half-force
+// velocity and Guo forcing of the central-moment model (reading), so they
+// differ from it only in where relaxation happens
+// ---------------------------------------------------------------------------
+
+// rho - 1 and j of pulled deviations from the x-line sums (53 additions).
+template <typename R> __host__ __device__ __forceinline__ void mass_momentum(const R (&f)[3][3][3], R &drho, R &jx, R &jy, R &jz)
+{
+    R X0[3][3], X1[3][3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+            X1[z][y] = f[z][y][2] - f[z][y][0];
+            X0[z][y] = (f[z][y][2] + f[z][y][0]) + f[z][y][1];
+        }
+    R Z0[3], Y1[3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z) {
+        Z0[z] = (X0[z][2] + X0[z][0]) + X0[z][1];
+        Y1[z] = X0[z][2] - X0[z][0];
+    }
+    drho = (Z0[2] + Z0[0]) + Z0[1];
+    jz = Z0[2] - Z0[0];
+    jy = (Y1[2] + Y1[0]) + Y1[1];
+    jx = ((X1[0][0] + X1[0][1]) + (X1[0][2] + X1[1][0])) + ((X1[1][1] + X1[1][2]) + (X1[2][0] + (X1[2][1] + X1[2][2])));
+}
+
+// Lattice BGK at rate omega = s_nu: f' = f - omega (f - f_eq(rho, u)) +
+// (1 - omega/2) G with the product-form f_eq = rho Phi(u), Phi =
+// phi(u_x) phi(u_y) phi(u_z), and G = F . dPhi/du.  In deviations
+// (d = f - w, w = Phi(0)):
+//   d' = (1 - omega) d + omega [(Phi - Phi0) + drho Phi] + h G,  h = 1 - omega/2,
+// evaluated as a sum of three tensor products grouped by the x factor,
+//   omega[...] + h G = A_x (omega drho B + h E) + (omega Q_x + h F_x D_x) B + omega P_x C,
+// with per-axis vectors P = phi(0), Q = phi(u) - phi(0), A = phi(u),
+// D = dphi/du and per-(y,z) products B = A_y A_z, C = Q_y A_z + P_y Q_z,
+// E = F_y D_y A_z + A_y F_z D_z.  No O(1) terms cancel.
+template <typename R>
+__host__ __device__ __forceinline__ void collide_bgk(R (&f)[3][3][3], R Fx, R Fy, R Fz, const Rates<R> &rt, R &rho_o,
+                                                     R &ux_o, R &uy_o, R &uz_o)
+{
+    R drho, jx, jy, jz;
+    mass_momentum(f, drho, jx, jy, jz);
+    const R inv = (R)1 / ((R)1 + drho);
+    const R u[3] = {(jx + (R)0.5 * Fx) * inv, (jy + (R)0.5 * Fy) * inv, (jz + (R)0.5 * Fz) * inv};
+    rho_o = (R)1 + drho;
+    ux_o = u[0];
+    uy_o = u[1];
+    uz_o = u[2];
+    const R om = rt.s_nu, h = (R)1 - (R)0.5 * rt.s_nu;
+    const R P[3] = {(R)(1.0 / 6.0), (R)(2.0 / 3.0), (R)(1.0 / 6.0)};  // index c + 1
+    R Q[3][3], A[3][3], D[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R v = u[a], v2 = v * v;
+        Q[a][0] = (R)0.5 * (v2 - v);
+        Q[a][1] = -v2;
+        Q[a][2] = (R)0.5 * (v2 + v);
+        D[a][0] = v - (R)0.5;
+        D[a][1] = (R)-2 * v;
+        D[a][2] = v + (R)0.5;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) A[a][c] = P[c] + Q[a][c];
+    }
+    const R omd = om * drho, hFx = h * Fx;
+    R V2[3], V3[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        V2[c] = om * Q[0][c] + hFx * D[0][c];
+        V3[c] = om * P[c];
+    }
+    const R keep = (R)1 - om;
+#pragma unroll
+    for (int z = 0; z < 3; ++z) {
+        const R FzDz = Fz * D[2][z];
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+            const R B = A[1][y] * A[2][z];
+            const R C = Q[1][y] * A[2][z] + P[y] * Q[2][z];
+            const R E = (Fy * D[1][y]) * A[2][z] + A[1][y] * FzDz;
+            const R M1 = omd * B + h * E;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) f[z][y][x] = keep * f[z][y][x] + (A[0][x] * M1 + (V2[x] * B + V3[x] * C));
+        }
+    }
+}
+
+// Raw-moment MRT: the combination basis of the central-moment model taken
+// about zero velocity.  Raw moments of d; equilibrium raw moments of the
+// product form, rho prod_a r_e(u_a) with r_0 = 1, r_1 = u, r_2 = 1/3 + u^2,
+// in deviations drho prod r(u) + (prod r(u) - prod r(0)) expanded per axis;
+// force moments sum_a F_a d/du_a prod r(u); relaxation per group as in
+// relax() (deviator / trace split of the second-order diagonal), then the
+// inverse raw transform.
+template <typename R>
+__host__ __device__ __forceinline__ void collide_rm(R (&f)[3][3][3], R Fx, R Fy, R Fz, const Rates<R> &rt, R &rho_o,
+                                                    R &ux_o, R &uy_o, R &uz_o)
+{
+    raw_all(f);  // raw moments of d, index [c][b][a]
+    R drho, ux, uy, uz;
+    velocity(f, Fx, Fy, Fz, drho, ux, uy, uz);
+    rho_o = (R)1 + drho;
+    ux_o = ux;
+    uy_o = uy;
+    uz_o = uz;
+    const R u[3] = {ux, uy, uz};
+    const R F[3] = {Fx, Fy, Fz};
+    const R third = (R)(1.0 / 3.0);
+    R r[3][3], q[3][3], dr[3][3];  // [axis][exponent]: r(u), r(u) - r(0), dr/du
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R v = u[a], v2 = v * v;
+        r[a][0] = (R)1;
+        r[a][1] = v;
+        r[a][2] = third + v2;
+        q[a][0] = (R)0;
+        q[a][1] = v;
+        q[a][2] = v2;
+        dr[a][0] = (R)0;
+        dr[a][1] = (R)1;
+        dr[a][2] = (R)2 * v;
+    }
+    const R r0[3] = {(R)1, (R)0, third};
+    R neq[3][3][3], mF[3][3][3];  // m - m_eq and the force moments
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R ryz = r[1][b] * r[2][c];
+                const R Rabc = r[0][a] * ryz;
+                const R dev = q[0][a] * ryz + r0[a] * (q[1][b] * r[2][c] + r0[b] * q[2][c]);
+                neq[c][b][a] = f[c][b][a] - (drho * Rabc + dev);
+                mF[c][b][a] = F[0] * dr[0][a] * ryz + r[0][a] * (F[1] * dr[1][b] * r[2][c] + r[1][b] * F[2] * dr[2][c]);
+            }
+    // relaxation: m' = m - S (m - m_eq) + (I - S/2) m_F; orders 0 and 1 keep
+    // their moments and gain the force
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int n = a + b + c;
+                const bool diag2 = n == 2 && (a == 2 || b == 2 || c == 2);
+                if (n < 2) {
+                    f[c][b][a] += mF[c][b][a];
+                } else if (!diag2) {
+                    const R s = n == 2 ? rt.s_nu : n == 3 ? rt.s3 : n == 4 ? rt.s4 : n == 5 ? rt.s5 : rt.s6;
+                    f[c][b][a] += -s * neq[c][b][a] + ((R)1 - (R)0.5 * s) * mF[c][b][a];
+                }
+            }
+    {
+        const R tn = (rt.s_b - rt.s_nu) * third * (neq[0][0][2] + neq[0][2][0] + neq[2][0][0]);
+        const R tf = (rt.s_b - rt.s_nu) * third * (mF[0][0][2] + mF[0][2][0] + mF[2][0][0]);
+        f[0][0][2] += -(rt.s_nu * neq[0][0][2] + tn) + mF[0][0][2] - (R)0.5 * (rt.s_nu * mF[0][0][2] + tf);
+        f[0][2][0] += -(rt.s_nu * neq[0][2][0] + tn) + mF[0][2][0] - (R)0.5 * (rt.s_nu * mF[0][2][0] + tf);
+        f[2][0][0] += -(rt.s_nu * neq[2][0][0] + tn) + mF[2][0][0] - (R)0.5 * (rt.s_nu * mF[2][0][0] + tf);
+    }
     auto iraw = [](R &a, R &b, R &c) { iraw3(a, b, c); };
     lines_z(f, iraw);
     lines_y(f, iraw);
     lines_x(f, iraw);
+}
+
+// Collision by model: 0 central moments (any rates), 1 central moments with
+// unit rates of orders 3 to 6, 2 BGK, 3 raw-moment MRT.
+enum : int { COLL_CM = 0, COLL_CM_UNIT_HIGH = 1, COLL_BGK = 2, COLL_RM = 3 };
+template <int COLL, typename R>
+__host__ __device__ __forceinline__ void collide_as(R (&f)[3][3][3], R Fx, R Fy, R Fz, const Rates<R> &rt, R &rho_o,
+                                                    R &ux_o, R &uy_o, R &uz_o)
+{
+    if constexpr (COLL == COLL_CM_UNIT_HIGH) collide_unit_high(f, Fx, Fy, Fz, rt, rho_o, ux_o, uy_o, uz_o);
+    else if constexpr (COLL == COLL_BGK) collide_bgk(f, Fx, Fy, Fz, rt, rho_o, ux_o, uy_o, uz_o);
+    else if constexpr (COLL == COLL_RM) collide_rm(f, Fx, Fy, Fz, rt, rho_o, ux_o, uy_o, uz_o);
+    else collide(f, Fx, Fy, Fz, rt, rho_o, ux_o, uy_o, uz_o);
 }
 
 // rho - 1 and j of pulled deviations (no transform of the rest).

@@ -1,0 +1,422 @@
+// lbm_step.hpp -- the per-step kernels of liblbm (Alg. 2 of the paper):
+//   k_band      (a)+(b) on the immersed-boundary band only: pull + rho, u
+//   k_ib_run    (c) interpolation and penalty force per sample; per run of
+//               samples sharing a base cell, the 8 spreading sums
+//   k_ib_total  (c) FP64 total force and torque from per-block partials, in order
+//   k_spread    (c) spreading completed: each band node gathers its run sums
+//   k_fused     (a)+(b)+(d)+(e) for every node: pull with face rules, rho and
+//               u, band force, central-moment collision, store
+#pragma once
+
+#include "lbm_ctx.hpp"
+
+namespace lbm {
+
+template <typename R> struct R4T;
+template <> struct R4T<float> {
+    using type = float4;
+};
+template <> struct R4T<double> {
+    using type = double4;
+};
+
+template <int ST> struct StepParams {
+    using R = typename Store<ST>::R;
+    using T = typename Store<ST>::T;
+    using R4 = typename R4T<R>::type;
+    Geom g;
+    const T *__restrict__ fin;
+    T *__restrict__ fout;
+    Rates<R> rt;
+    R body[3];
+    Inlet<R> inlet;
+    const uint64_t *__restrict__ tile_mask;
+    const int32_t *__restrict__ tile_start;
+    const R4 *__restrict__ band_force;
+    const float *__restrict__ sc_in;
+    float *__restrict__ sc_out;
+    int sc_h;
+};
+
+// ---------------------------------------------------------------------------
+// passive scalar: first-order upwind by the collision velocity; periodic
+// wrap or zero gradient at faces; held at 1 on inlet nodes below sc_h
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int nb_coord(int v, int n, bool periodic)
+{
+    if (v < 0) return periodic ? v + n : 0;
+    if (v >= n) return periodic ? v - n : n - 1;
+    return v;
+}
+
+template <int ST>
+__device__ __forceinline__ void scalar_update(const StepParams<ST> &P, int x, int y, int z, float ux, float uy,
+                                              float uz, bool active)
+{
+    const Geom &g = P.g;
+    auto at = [&](int xx, int yy, int zz) {
+        xx = nb_coord(xx, g.nx, g.face[0] == LBM_PERIODIC);
+        yy = nb_coord(yy, g.ny, g.face[2] == LBM_PERIODIC);
+        zz = nb_coord(zz, g.nz, g.face[4] == LBM_PERIODIC);
+        return P.sc_in[((int64_t)zz * g.ny + yy) * g.nxp + xx];
+    };
+    const float s0 = at(x, y, z);
+    float v = s0;
+    v -= ux > 0.f ? ux * (s0 - at(x - 1, y, z)) : ux * (at(x + 1, y, z) - s0);
+    v -= uy > 0.f ? uy * (s0 - at(x, y - 1, z)) : uy * (at(x, y + 1, z) - s0);
+    v -= uz > 0.f ? uz * (s0 - at(x, y, z - 1)) : uz * (at(x, y, z + 1) - s0);
+    if (x == 0 && g.face[0] == LBM_INLET && y < P.sc_h) v = 1.f;
+    if (active) P.sc_out[((int64_t)z * g.ny + y) * g.nxp + x] = v;
+}
+
+// ---------------------------------------------------------------------------
+// fused step
+// ---------------------------------------------------------------------------
+// B32: the 27 populations of one row lie within 2^31 bytes of the row's start
+// (always for the blocked layout), so the stores go through a buffer
+// descriptor based at the row: population offset in a scalar register, x
+// offset in one 32-bit vector register, no 64-bit vector address arithmetic.
+//
+// ROW: the workgroup's waves are exactly the segments of one row (segments per
+// row == waves per workgroup) and x is periodic.  Rows on no y/z face then
+// stage the 27 source rows in LDS with aligned, coalesced loads (one per
+// population and node) and read the x-shifted values back from LDS, instead
+// of 18 misaligned global loads; all waves of a workgroup share the row, so
+// the barrier is uniform.
+//
+// COLL: the collision model (collide_as: central moments with any rates or
+// with unit high-order rates, BGK, raw-moment MRT).
+template <int ST, bool BAND, bool SCALAR, bool B32, bool ROW, int COLL>
+__global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams<ST> P)
+{
+    using R = typename Store<ST>::R;
+    using T = typename Store<ST>::T;
+    const Geom &g = P.g;
+    const int lane = threadIdx.x & (SEG - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / SEG);
+    const uint32_t w = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (uint32_t)wv;
+    if (w >= (uint32_t)g.W) return;
+    int xs, y, z;
+    wave_coords(w, g, xs, y, z);
+    const int x = xs * SEG + lane;
+    const bool active = x < g.nx;
+    const int xc = active ? x : g.nx - 1;
+
+    R f[3][3][3];
+    if constexpr (ROW) {
+        __shared__ T row[Q][SEG * WAVES_PER_BLOCK];
+        const bool yz = (y == 0 && g.face[2] != LBM_PERIODIC) || (y == g.ny - 1 && g.face[3] != LBM_PERIODIC) ||
+                        (z == 0 && g.face[4] != LBM_PERIODIC) || (z == g.nz - 1 && g.face[5] != LBM_PERIODIC);
+        if (yz) {
+            pull_general<ST>(f, P.fin, xc, y, z, g, P.inlet);
+        } else {
+            const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+            const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+            const int ysrc[3] = {yp, y, ym};
+            const int zsrc[3] = {zp, z, zm};
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    row[i][x] = P.fin[(int64_t)i * g.plane + row_off(g, ysrc[CY[i] + 1], zsrc[CZ[i] + 1]) + x];
+            }
+            __syncthreads();
+            const int xm = xc == 0 ? g.nx - 1 : xc - 1, xp = xc == g.nx - 1 ? 0 : xc + 1;
+            const int xsrc[3] = {xp, xc, xm};
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(row[i][xsrc[CX[i] + 1]]);
+        }
+    } else {
+        pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
+    }
+
+    R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
+    if (BAND) {
+        const uint64_t mask = P.tile_mask[w];
+        if (mask != 0 && ((mask >> lane) & 1ull)) {
+            const int slot = P.tile_start[w] + __popcll(mask & ((1ull << lane) - 1ull));
+            const auto F = P.band_force[slot];
+            Fx += F.x;
+            Fy += F.y;
+            Fz += F.z;
+        }
+    }
+    R rho, ux, uy, uz;
+    collide_as<COLL>(f, Fx, Fy, Fz, P.rt, rho, ux, uy, uz);
+    if (active) {
+        if constexpr (B32 && LBM_BUF_STORES) {
+            const BufRsrc rout = make_rsrc(P.fout + row_off(g, y, z), (uint32_t)(Q * g.plane * (int64_t)sizeof(T)));
+            const uint32_t xb = (uint32_t)(x * sizeof(T));
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                buf_st_nt<T>(Store<ST>::enc(f[CZ[i] + 1][CY[i] + 1][CX[i] + 1]), rout, xb,
+                             (uint32_t)i * (uint32_t)(g.plane * (int64_t)sizeof(T)));
+        } else {
+            const int64_t base = row_off(g, y, z) + x;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                __builtin_nontemporal_store(Store<ST>::enc(f[CZ[i] + 1][CY[i] + 1][CX[i] + 1]),
+                                            P.fout + (int64_t)i * g.plane + base);
+        }
+    }
+    if (SCALAR) scalar_update<ST>(P, xc, y, z, (float)ux, (float)uy, (float)uz, active);
+}
+
+// ---------------------------------------------------------------------------
+// band pre-pass: streamed rho and u0 = j/rho of every band node
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ void __launch_bounds__(256)
+    k_band(const StepParams<ST> P, const int32_t *__restrict__ band_cell, int64_t nband,
+           typename StepParams<ST>::R4 *__restrict__ band_ru)
+{
+    using R = typename Store<ST>::R;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nband) return;
+    const Geom &g = P.g;
+    const int64_t cell = band_cell[b];
+    const int x = (int)(cell % g.nx);
+    const int64_t r = cell / g.nx;
+    const int y = (int)(r % g.ny), z = (int)(r / g.ny);
+    const Macro<R> m = node_moments<ST>(P.fin, x, y, z, g, P.inlet);
+    const R rho = (R)1 + m.drho, inv = (R)1 / rho;
+    typename StepParams<ST>::R4 v;
+    v.x = rho;
+    v.y = m.jx * inv;
+    v.z = m.jy * inv;
+    v.w = m.jz * inv;
+    band_ru[b] = v;
+}
+
+// ---------------------------------------------------------------------------
+// immersed boundary (Eqs. 6-8), spreading in two deterministic phases
+//   k_ib_run: one lane per run of sorted samples sharing a base cell (the
+//     samples of one cell are contiguous, Sec. 4.2.2 order).  The run's 8
+//     stencil nodes and their (rho, u0) are loaded once; each sample adds
+//     a_s K_d g_s to a register accumulator per offset d; the run stores its
+//     8 sums (no atomics).
+//   k_spread: one lane per band node gathers the (at most 8) run sums that
+//     target it, in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename R> struct IbParams {
+    using R4 = typename R4T<R>::type;
+    int64_t n, nruns, nband;
+    const int32_t *__restrict__ run_start;  // [nruns + 1]
+    const float *__restrict__ pos;          // [3][n] sorted
+    const float *__restrict__ ub;           // [3][n]
+    const float *__restrict__ area;         // [n]
+    const float *__restrict__ gain;         // [n]
+    const int32_t *__restrict__ slot;       // [8][n]
+    const R4 *__restrict__ band_ru;
+    R4 *__restrict__ run_sum;               // [8][nruns]
+    double *__restrict__ part;              // [gridDim.x][8] per-block force and torque totals
+    double ox, oy, oz;                      // reference point of the torque
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_ib_run(const IbParams<R> P)
+{
+    using R4 = typename R4T<R>::type;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t n = P.n;
+    double tot[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // force, then torque about (ox, oy, oz)
+    if (r < P.nruns) {
+        const int64_t k0 = P.run_start[r], k1 = P.run_start[r + 1];
+        R4 node[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) node[d] = P.band_ru[P.slot[(int64_t)d * n + k0]];
+        R acc[8][3];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) acc[d][0] = acc[d][1] = acc[d][2] = (R)0;
+        for (int64_t k = k0; k < k1; ++k) {
+            R t[3];
+            float p[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                p[a] = P.pos[a * n + k];
+                t[a] = (R)(p[a] - floorf(p[a]));
+            }
+            R K[8], rs = 0, us[3] = {0, 0, 0};
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                K[d] = ((d & 1) ? t[0] : (R)1 - t[0]) * ((d & 2) ? t[1] : (R)1 - t[1]) * ((d & 4) ? t[2] : (R)1 - t[2]);
+                rs += K[d] * node[d].x;
+                us[0] += K[d] * node[d].y;
+                us[1] += K[d] * node[d].z;
+                us[2] += K[d] * node[d].w;
+            }
+            // Eq. (7) with the sample's gain; Eq. (8) carries the area weight
+            const R ag = (R)P.area[k] * (R)P.gain[k] * rs;
+            R aG[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                aG[a] = ag * ((R)P.ub[a * n + k] - us[a]);
+                tot[a] += (double)aG[a];
+            }
+            // Alg. 2 (c) torque: (x_s - o) x (a_s g_s), lever arm in FP64
+            const double rx = (double)p[0] - P.ox, ry = (double)p[1] - P.oy, rz = (double)p[2] - P.oz;
+            tot[3] += ry * (double)aG[2] - rz * (double)aG[1];
+            tot[4] += rz * (double)aG[0] - rx * (double)aG[2];
+            tot[5] += rx * (double)aG[1] - ry * (double)aG[0];
+#pragma unroll
+            for (int d = 0; d < 8; ++d)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) acc[d][a] += K[d] * aG[a];
+        }
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            R4 v;
+            v.x = acc[d][0];
+            v.y = acc[d][1];
+            v.z = acc[d][2];
+            v.w = (R)0;
+            P.run_sum[(int64_t)d * P.nruns + r] = v;
+        }
+    }
+    // FP64 total force and torque: wave reduction, then one partial per block
+    // (no same-address atomics; the partials are summed in order afterwards)
+    __shared__ double wsum[4][6];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) tot[a] += __shfl_down(tot[a], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) wsum[threadIdx.x >> 6][a] = tot[a];
+    __syncthreads();
+    if (threadIdx.x < 6)
+        P.part[8 * blockIdx.x + threadIdx.x] =
+            wsum[0][threadIdx.x] + wsum[1][threadIdx.x] + wsum[2][threadIdx.x] + wsum[3][threadIdx.x];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_spread(int64_t nband, int64_t nruns, const int32_t *__restrict__ band_src,
+                                                const typename R4T<R>::type *__restrict__ run_sum,
+                                                typename R4T<R>::type *__restrict__ band_force)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nband) return;
+    typename R4T<R>::type g;
+    g.x = g.y = g.z = g.w = (R)0;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const int32_t src = band_src[(int64_t)d * nband + j];
+        if (src >= 0) {
+            const auto v = run_sum[(int64_t)d * nruns + src];
+            g.x += v.x;
+            g.y += v.y;
+            g.z += v.z;
+        }
+    }
+    band_force[j] = g;
+}
+
+// ordered sum of the per-block force and torque partials (deterministic FP64 totals);
+// a template so that every storage's translation unit may hold its copy
+template <int UNUSED = 0>
+__global__ void __launch_bounds__(256) k_ib_total(const double *__restrict__ part, int nblk, double *__restrict__ ftot)
+{
+    __shared__ double sh[6][256];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) acc[a] += part[8 * b + a];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) sh[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int a = 0; a < 6; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) ftot[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int ST> StepParams<ST> make_params(lbm_ctx *c)
+{
+    using R = typename Store<ST>::R;
+    using T = typename Store<ST>::T;
+    StepParams<ST> P{};
+    P.g = c->g;
+    P.fin = static_cast<const T *>(c->fA);
+    P.fout = static_cast<T *>(c->fB);
+    P.rt = {(R)c->s_nu, (R)c->s_b, (R)c->s_h[0], (R)c->s_h[1], (R)c->s_h[2], (R)c->s_h[3]};
+    for (int a = 0; a < 3; ++a) {
+        P.body[a] = (R)c->p.body_force[a];
+        P.inlet.u[a] = (R)c->p.u_in[a];
+    }
+    P.inlet.prof = static_cast<const R *>(c->p.inlet_profile);
+    P.tile_mask = c->tile_mask;
+    P.tile_start = c->tile_start;
+    P.band_force = static_cast<const typename StepParams<ST>::R4 *>(c->band_force);
+    P.sc_in = c->scA;
+    P.sc_out = c->scB;
+    P.sc_h = c->p.scalar_inlet_height;
+    return P;
+}
+
+static inline unsigned blocks_for_items(int64_t W) { return (unsigned)((W + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK); }
+
+template <int ST, bool B32, int COLL> static void fused_launch(lbm_ctx *c, const StepParams<ST> &P)
+{
+    const bool band = c->nm > 0, scalar = c->p.passive_scalar != 0;
+    const dim3 grid(blocks_for_items(c->g.W)), block(SEG * WAVES_PER_BLOCK);
+    if (band && scalar) hipLaunchKernelGGL((k_fused<ST, true, true, B32, false, COLL>), grid, block, 0, c->stream, P);
+    else if (band) hipLaunchKernelGGL((k_fused<ST, true, false, B32, false, COLL>), grid, block, 0, c->stream, P);
+    else if (scalar) hipLaunchKernelGGL((k_fused<ST, false, true, B32, false, COLL>), grid, block, 0, c->stream, P);
+    else if (B32 && c->row_stage)
+        hipLaunchKernelGGL((k_fused<ST, false, false, B32, B32, COLL>), grid, block, 0, c->stream, P);
+    else hipLaunchKernelGGL((k_fused<ST, false, false, B32, false, COLL>), grid, block, 0, c->stream, P);
+}
+
+// the fused step of one storage form and one collision model
+template <int ST, int COLL> hipError_t fused_st(lbm_ctx *c)
+{
+    const StepParams<ST> P = make_params<ST>(c);
+    if constexpr (ST != LBM_F64) {
+        if (c->buffer_path) fused_launch<ST, true, COLL>(c, P);
+        else fused_launch<ST, false, COLL>(c, P);
+    } else {
+        fused_launch<ST, false, COLL>(c, P);
+    }
+    return hipGetLastError();
+}
+
+template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *ftot)
+{
+    using R = typename Store<ST>::R;
+    using R4 = typename StepParams<ST>::R4;
+    StepParams<ST> P = make_params<ST>(c);
+    P.fin = static_cast<const typename Store<ST>::T *>(state);
+    const unsigned nb = (unsigned)((c->nband + 255) / 256);
+    hipLaunchKernelGGL((k_band<ST>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, P, c->band_cell, c->nband,
+                       static_cast<R4 *>(c->band_ru));
+    IbParams<R> Q{};
+    Q.n = c->nm;
+    Q.nruns = c->nruns;
+    Q.nband = c->nband;
+    Q.run_start = c->run_start;
+    Q.pos = c->m_pos;
+    Q.ub = c->m_ub;
+    Q.area = c->m_area;
+    Q.gain = c->m_gain;
+    Q.slot = c->m_slot;
+    Q.band_ru = static_cast<const R4 *>(c->band_ru);
+    Q.run_sum = static_cast<R4 *>(c->run_sum);
+    Q.part = c->ib_part;
+    Q.ox = c->pose_o[0];
+    Q.oy = c->pose_o[1];
+    Q.oz = c->pose_o[2];
+    const int nblk = (int)((c->nruns + 255) / 256);
+    hipLaunchKernelGGL((k_ib_run<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
+    hipLaunchKernelGGL(k_ib_total<>, dim3(1), dim3(256), 0, c->stream, c->ib_part, nblk, ftot);
+    hipLaunchKernelGGL((k_spread<R>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, c->nband, c->nruns,
+                       c->band_src, static_cast<const R4 *>(c->run_sum), static_cast<R4 *>(c->band_force));
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -18,6 +18,8 @@ LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 PERIODIC, NOSLIP, FREESLIP, INLET, OUTFLOW = 0, 1, 2, 3, 4
 F32, F16DEV, BF16DEV, F64 = 0, 1, 2, 3
 STORAGE = {"f32": F32, "f16": F16DEV, "bf16": BF16DEV, "f64": F64}
+CM, BGK, RMMRT = 0, 1, 2
+COLLISION = {"cm": CM, "bgk": BGK, "rm": RMMRT}
 STATUS = {0: "LBM_OK", 1: "LBM_E_INVAL", 2: "LBM_E_NOMEM", 3: "LBM_E_HIP", 4: "LBM_E_NONFINITE",
           5: "LBM_E_STATE", 6: "LBM_E_UNSUPPORTED"}
 
@@ -41,6 +43,7 @@ class Params(C.Structure):
         ("storage", C.c_int32),
         ("passive_scalar", C.c_int32),
         ("scalar_inlet_height", C.c_int32),
+        ("collision", C.c_int32),
     ]
 
 
@@ -139,7 +142,7 @@ def _need(t: torch.Tensor | None, nbytes: int, what: str, dtype=None):
 
 def make_params(nx, ny, nz, nu, faces=(PERIODIC,) * 6, u_in=(0.0, 0.0, 0.0), body=(0.0, 0.0, 0.0),
                 s_bulk=1.0, s_high=(1.0, 1.0, 1.0, 1.0), storage="f32", scalar=False,
-                scalar_inlet_height=0) -> Params:
+                scalar_inlet_height=0, collision="cm") -> Params:
     p = Params()
     _check(_L.lbm_default_params(C.byref(p), nx, ny, nz, float(nu)))
     for k in range(6):
@@ -153,6 +156,7 @@ def make_params(nx, ny, nz, nu, faces=(PERIODIC,) * 6, u_in=(0.0, 0.0, 0.0), bod
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     p.passive_scalar = 1 if scalar else 0
     p.scalar_inlet_height = int(scalar_inlet_height)
+    p.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
     return p
 
 
@@ -172,13 +176,14 @@ class Solver:
 
     def __init__(self, nx, ny, nz, nu, faces=(PERIODIC,) * 6, u_in=(0.0, 0.0, 0.0), inlet_profile=None,
                  body=(0.0, 0.0, 0.0), s_bulk=1.0, s_high=(1.0, 1.0, 1.0, 1.0), storage="f32", scalar=False,
-                 scalar_inlet_height=0, device="cuda", stream=None):
+                 scalar_inlet_height=0, collision="cm", device="cuda", stream=None):
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
         self.device = torch.device(device)
         self.storage = storage
         self.real = torch.float64 if storage == "f64" else torch.float32
-        self._p = make_params(nx, ny, nz, nu, faces, u_in, body, s_bulk, s_high, storage, scalar, scalar_inlet_height)
+        self._p = make_params(nx, ny, nz, nu, faces, u_in, body, s_bulk, s_high, storage, scalar, scalar_inlet_height,
+                              collision)
         self._inlet = None
         if inlet_profile is not None:
             self._inlet = self._real(inlet_profile, (3, nz, ny))

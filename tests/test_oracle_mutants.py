@@ -17,7 +17,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
 PINS = ["tests/test_oracle_moments.py", "tests/test_oracle_flows.py", "tests/test_oracle_ib.py",
-        "tests/test_oracle_motion.py"]
+        "tests/test_oracle_motion.py", "tests/test_oracle_models.py"]
 SKIP_SLOW = "not taylor_green_decay_rate and not magic_odd_rates"   # 15 s of the suite; never the only catcher
 
 # name: (text in lbm_oracle.c, replacement)
@@ -64,6 +64,17 @@ MUTANTS = {
                             "const double F[3] = {S->Gs[s], S->Gs[n + s], S->Gs[2 * n + s]};"),
     "torque_lever_reversed": ("const double r[3] = {(double)S->mx[s] - o[0], (double)S->mx[n + s] - o[1], (double)S->mx[2 * n + s] - o[2]};",
                               "const double r[3] = {o[0] - (double)S->mx[s], o[1] - (double)S->mx[n + s], o[2] - (double)S->mx[2 * n + s]};"),
+    # comparison collision models (Sec. 5.1): BGK and raw-moment MRT
+    "bgk_force_factor": ("+ (1.0 - 0.5 * omega) * G[i];", "+ (1.0 - omega) * G[i];"),
+    "bgk_equilibrium_without_half_force": ("    orc_equilibrium(rho, u, feq);\n    orc_forcing_shape(u, F, G);\n    for (int i = 0; i < Q; ++i) fpost[i]",
+                                           "    const double u0[3] = {u[0] - 0.5 * F[0] / rho, u[1] - 0.5 * F[1] / rho, u[2] - 0.5 * F[2] / rho};\n    orc_equilibrium(rho, u0, feq);\n    orc_forcing_shape(u, F, G);\n    for (int i = 0; i < Q; ++i) fpost[i]"),
+    "models_no_half_force_shift": ("u[a] = (j[a] + F[a] / 2.0) / rho;", "u[a] = j[a] / rho;"),
+    "forcing_shape_derivative_sign": ("dphi[a] = (CV[i][a] + 2.0 * ua) * 0.5;", "dphi[a] = (CV[i][a] - 2.0 * ua) * 0.5;"),
+    "rm_moments_about_u": ("orc_basis_matrix(zero, M0);", "orc_basis_matrix(u, M0);"),
+    "rm_force_moments_dropped": ("mp[k] = m - s * (m - me) + (1.0 - 0.5 * s) * mf;", "mp[k] = m - s * (m - me);"),
+    "rm_trace_rate": ("        const double s = rate_of(k, s_nu, s_b, s_high);\n        mp[k] = m - s",
+                      "        const double s = rate_of(k == 9 ? 7 : k, s_nu, s_b, s_high);\n        mp[k] = m - s"),
+    "model_switch_swapped": ("if (S->model == 1) rc = orc_collide_bgk", "if (S->model == 2) rc = orc_collide_bgk"),
     # passive scalar (reading R21)
     "scalar_downwind": ("if (u[a] > 0.0) v -= u[a]", "if (u[a] < 0.0) v -= u[a]"),
     "scalar_inlet_height_off_by_one": ("y < S->scalar_inlet_height) v = 1.0;", "y <= S->scalar_inlet_height) v = 1.0;"),
