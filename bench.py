@@ -90,11 +90,41 @@ def measured_copy(solver, reps=5):
     return 2 * solver.state_bytes() * reps / t / 1e9
 
 
-def turbulence_solver(n, storage, rho, u):
+def turbulence_solver(n, storage, rho, u, collision="cm"):
     from paper_2101_11856_amd import lbm
-    s = lbm.Solver(n, n, n, 1e-4, storage=storage)
+    s = lbm.Solver(n, n, n, 1e-4, storage=storage, collision=collision)
     s.init_equilibrium(rho, u)
     return s
+
+
+def collision_models(n, rho, u, steps, warmup):
+    """Cost of the collision models in the fused step (the paper's Sec. 5.1
+    compares its central-moment model with BGK and raw-moment MRT): the
+    headline workload per model and storage form.  "cm" is the default form
+    (unit rates of orders 3-6, specialised), "cm_general" the general
+    central-moment form at the same rates."""
+    import torch
+    out = {}
+    for storage in ("f32", "f16"):
+        for name, coll, env in (("cm", "cm", None), ("cm_general", "cm", "1"), ("bgk", "bgk", None),
+                                ("rm", "rm", None)):
+            old = os.environ.pop("LBM_CM_GENERAL", None)
+            if env:
+                os.environ["LBM_CM_GENERAL"] = env
+            try:
+                s = turbulence_solver(n, storage, rho, u, collision=coll)
+            finally:
+                os.environ.pop("LBM_CM_GENERAL", None)
+                if old is not None:
+                    os.environ["LBM_CM_GENERAL"] = old
+            t = timed_steps(s, steps, warmup) / steps
+            out[f"{name}_{storage}"] = {"ms_per_step": round(1e3 * t, 4), "MLUPS": round(n ** 3 / t / 1e6, 1)}
+            del s
+            torch.cuda.empty_cache()
+    for storage in ("f32", "f16"):
+        out[f"cm_over_bgk_time_{storage}"] = round(out[f"cm_{storage}"]["ms_per_step"] /
+                                                   out[f"bgk_{storage}"]["ms_per_step"], 3)
+    return out
 
 
 def cpu_baseline(rho, u, n, budget_s=20.0):
@@ -120,7 +150,30 @@ def cpu_baseline(rho, u, n, budget_s=20.0):
                       f"turbulence field ({cells} cells, {dt:.1f} s)"}
 
 
-def sphere_workload(steps, warmup, storage="f32"):
+def step_roofline(cells, storage, band, samples, scalar, t_step):
+    """HBM roofline of one whole step: algorithmic bytes per step (27 reads +
+    27 writes per node; per band node its pulled populations, (rho, u) and
+    force; per sample its position, velocity, area, gain, cell and spreading
+    share; the scalar's read and write) over the measured step time."""
+    b = 4 if storage == "f32" else 8 if storage == "f64" else 2
+    byts = cells * 54 * b + band * (27 * b + 16 + 12) + samples * 52 + (8 * cells if scalar else 0)
+    achieved = byts / t_step / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": int(byts),
+            "scope": "whole step (all kernels)"}
+
+
+def health(s, c0):
+    """Mass drift since c0 and the non-finite check of the stored state."""
+    from paper_2101_11856_amd import lbm
+    try:
+        c1 = s.conserved()
+    except lbm.LbmError as e:
+        return {"finite": False, "error": str(e)}
+    return {"finite": True, "mass_drift_rel": float(abs(c1[0] - c0[0]) / c0[0])}
+
+
+def sphere_workload(steps, warmup, storage="f32", n_sphere=13000, n_random=200000):
     import torch
 
     from paper_2101_11856_amd import lbm, synth
@@ -129,18 +182,85 @@ def sphere_workload(steps, warmup, storage="f32"):
                    storage=storage)
     rho, u = synth.uniform(nx, ny, nz, (0.05, 0.0, 0.0))
     s.init_equilibrium(rho, u)
-    xyz, ub, area, gain = synth.sphere_scene()
+    xyz, ub, area, gain = synth.sphere_scene(n_sphere=n_sphere, n_random=n_random)
     s.set_solids(xyz, ub, area, gain)
     band = int((s.solid_maps()[0] & 1).sum())
+    c0 = s.conserved()
     t = timed_steps(s, steps, warmup)
     F = s.ib_force()
-    out = {"workload": "flow past an immersed sphere 512x128x128, inlet/outflow, 13000 sphere + 200000 "
-                       f"random samples, {storage.upper()}", "value": round(nx * ny * nz * steps / t / 1e6, 1),
+    what = f"{n_sphere} sphere + {n_random} random samples" if n_random else f"{n_sphere} sphere samples"
+    out = {"workload": f"flow past an immersed sphere 512x128x128, inlet/outflow, {what}, {storage.upper()}",
+           "value": round(nx * ny * nz * steps / t / 1e6, 1),
            "unit": "MLUPS", "ms_per_step": round(1e3 * t / steps, 4), "samples": int(xyz.shape[1]),
-           "band_nodes": band, "drag_x": float(-F[0])}
+           "band_nodes": band, "drag_x": float(-F[0]),
+           "roofline": step_roofline(nx * ny * nz, storage, band, int(xyz.shape[1]), False, t / steps),
+           "health": health(s, c0)}
     del s
     torch.cuda.empty_cache()
     return out
+
+
+def dense_sphere_workload(steps, warmup, n_sphere=150000):
+    """The sphere of the sphere workload sampled at the paper's density
+    (Sec. 3.1: 10-100 samples per near-boundary cell): 150,000 Fibonacci
+    samples, no random box.  Timed with the default wavefront-scan spreading
+    and with one lane per run, next to the same grid with no samples; the
+    run-length statistics are those of the sorted samples."""
+    import numpy as np
+    import torch
+
+    from paper_2101_11856_amd import lbm, synth
+    nx, ny, nz = 512, 128, 128
+    xyz, ub, area, gain = synth.sphere_scene(n_sphere=n_sphere, n_random=0)
+    rho, u = synth.uniform(nx, ny, nz, (0.05, 0.0, 0.0))
+
+    def run(samples, lane_per_run=False):
+        old = os.environ.pop("LBM_IB_LANE_PER_RUN", None)
+        if lane_per_run:
+            os.environ["LBM_IB_LANE_PER_RUN"] = "1"
+        try:
+            s = lbm.Solver(nx, ny, nz, 5e-5, faces=(lbm.INLET, lbm.OUTFLOW, 0, 0, 0, 0), u_in=(0.05, 0.0, 0.0))
+        finally:
+            os.environ.pop("LBM_IB_LANE_PER_RUN", None)
+            if old is not None:
+                os.environ["LBM_IB_LANE_PER_RUN"] = old
+        s.init_equilibrium(rho, u)
+        info = {}
+        if samples:
+            s.set_solids(xyz, ub, area, gain)
+            fl, cell, perm = (t.cpu().numpy() for t in s.solid_maps())
+            info["band"] = int((fl & 1).sum())
+            sc = cell[perm]                                   # base cell of each sorted sample
+            _, counts = np.unique(sc, return_counts=True)
+            info["per_cell"] = counts
+            starts = np.r_[0, np.flatnonzero(np.diff(sc)) + 1]
+            lens = np.diff(np.r_[starts, sc.size])            # samples per cell in sorted order
+            w = lens[: lens.size // 64 * 64].reshape(-1, 64)  # 64 cells per wavefront of the lane-per-run form
+            info["wave_max_over_mean"] = float((w.max(axis=1) / w.mean(axis=1)).mean())
+            info["F"] = None
+        t = timed_steps(s, steps, warmup)
+        if samples:
+            info["F"] = s.ib_force()
+        del s
+        torch.cuda.empty_cache()
+        return t / steps, info
+
+    t_plain, _ = run(False)
+    t_seg, info = run(True)
+    t_lpr, info2 = run(True, lane_per_run=True)
+    pc = info["per_cell"]
+    return {"workload": f"immersed sphere 512x128x128 at the paper's sampling density, {n_sphere} samples, FP32",
+            "value": round(nx * ny * nz / t_seg / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(1e3 * t_seg, 4),
+            "samples": int(xyz.shape[1]), "band_nodes": info["band"],
+            "samples_per_base_cell": {"mean": round(float(pc.mean()), 1), "max": int(pc.max()),
+                                      "p10": float(np.percentile(pc, 10)), "p90": float(np.percentile(pc, 90))},
+            "lane_per_run_wave_max_over_mean_run": round(info["wave_max_over_mean"], 2),
+            "no_samples_ms_per_step": round(1e3 * t_plain, 4),
+            "ib_share_of_step": round((t_seg - t_plain) / t_seg, 4),
+            "lane_per_run_ms_per_step": round(1e3 * t_lpr, 4),
+            "lane_per_run_ib_share_of_step": round((t_lpr - t_plain) / t_lpr, 4),
+            "drag_x": float(-info["F"][0]), "drag_x_lane_per_run": float(-info2["F"][0]),
+            "roofline": step_roofline(nx * ny * nz, "f32", info["band"], int(xyz.shape[1]), False, t_seg)}
 
 
 def city_workload(steps, warmup, storage="f32"):
@@ -161,12 +281,15 @@ def city_workload(steps, warmup, storage="f32"):
     xyz, ub, area, gain = synth.city_markers(synth.city_boxes())
     s.set_solids(xyz, ub, area, gain)
     band = int((s.solid_maps()[0] & 1).sum())
+    c0 = s.conserved()
     t = timed_steps(s, steps, warmup)
     cells = nx * ny * nz
     out = {"workload": f"city blocks 1200x250x840, {xyz.shape[1]} samples, passive scalar, {storage.upper()}",
            "value": round(cells * steps / t / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(1e3 * t / steps, 3),
            "samples": int(xyz.shape[1]), "band_nodes": band, "cells": cells,
-           "population_bytes": 2 * 27 * cells * (4 if storage == "f32" else 2)}
+           "population_bytes": 2 * 27 * cells * (4 if storage == "f32" else 2),
+           "roofline": step_roofline(cells, storage, band, int(xyz.shape[1]), True, t / steps),
+           "health": dict(health(s, c0), steps=warmup + steps)}
     del s
     torch.cuda.empty_cache()
     return out
@@ -220,9 +343,81 @@ def moving_torus_workload(steps, warmup):
            "value": round(cells * steps / t / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(1e3 * t / steps, 4),
            "static_ms_per_step": round(1e3 * t_static / steps, 4),
            "replace_ms_per_step": round(1e3 * (t - t_static) / steps, 4),
-           "samples": n, "band_nodes_at_start": band0, "torque_on_fluid": [float(x) for x in T]}
+           "samples": n, "band_nodes_at_start": band0, "torque_on_fluid": [float(x) for x in T],
+           "roofline": dict(step_roofline(cells, "f32", band0, n, False, t / steps),
+                            scope="whole moving step (re-placement included, its bytes not counted)"),
+           "roofline_static": step_roofline(cells, "f32", band0, n, False, t_static / steps)}
     del s
     torch.cuda.empty_cache()
+    return out
+
+
+def oracle_errors(steps=100, n=64):
+    """Part of the CPU-baseline leg (the only leg that runs the oracle): error
+    of each storage form against the FP64 oracle, on the same seeded inputs:
+    the turbulence generator on an n^3 periodic box (the headline's field at
+    reduced size), and an immersed-boundary scene at the paper's sampling
+    density (70x18x16 channel, inlet/outflow, no-slip and free-slip walls; a
+    sphere with about 44 samples per base cell plus a cluster of about 375 per
+    cell).  rel-L2 over all nodes after `steps` steps."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as O
+    from paper_2101_11856_amd import lbm, synth
+
+    def rel(a, b):
+        return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+    out = {}
+    rho, u = synth.turbulence(n)
+    S = O.OracleSim(n, n, n, 1e-4)
+    S.init_equilibrium(rho.astype(np.float64), u.astype(np.float64))
+    S.step(steps)
+    r_ref, u_ref = S.macros()
+    res = {}
+    for storage in ("f32", "f16", "bf16"):
+        sv = lbm.Solver(n, n, n, 1e-4, storage=storage)
+        sv.init_equilibrium(rho, u)
+        sv.step(steps)
+        r, uu = (t.cpu().double().numpy() for t in sv.macros())
+        res[storage] = {"u_rel_l2": rel(uu, u_ref), "rho_rel_l2": rel(r, r_ref)}
+        del sv
+    out["turbulence"] = {"case": f"turbulence {n}^3 periodic, nu=1e-4, {steps} steps", **res}
+
+    nx, ny, nz = 70, 18, 16
+    faces = (lbm.INLET, lbm.OUTFLOW, lbm.NOSLIP, lbm.FREESLIP, 0, 0)
+    rng = np.random.default_rng(31)
+    sph = synth.fibonacci_sphere(20000, 5.0, (14.3, ny / 2 + 0.2, nz / 2 - 0.1))
+    clu = synth.random_box(3000, (40.0, 8.0, 7.0), (42.0, 10.0, 9.0), 32)
+    xyz = np.concatenate([sph, clu], axis=1)
+    m = xyz.shape[1]
+    ub = np.zeros((3, m), np.float32)
+    area = np.concatenate([np.full(20000, 4 * np.pi * 25.0 / 20000), np.full(3000, 8.0 / 3000)]).astype(np.float32)
+    gain = np.ones(m, np.float32)
+    rho = (1.0 + 1e-3 * rng.standard_normal((nz, ny, nx))).astype(np.float32)
+    u = np.zeros((3, nz, ny, nx), np.float32)
+    u[0] = 0.03
+    S = O.OracleSim(nx, ny, nz, 1e-3, faces=faces, u_in=(0.03, 0, 0))
+    S.set_markers(xyz, ub.astype(np.float64), area.astype(np.float64), gain.astype(np.float64))
+    S.init_equilibrium(rho.astype(np.float64), u.astype(np.float64))
+    S.step(steps)
+    r_ref, u_ref = S.macros()
+    F_ref = S.last_force()
+    res = {}
+    for storage in ("f32", "f16", "bf16"):
+        sv = lbm.Solver(nx, ny, nz, 1e-3, storage=storage, faces=faces, u_in=(0.03, 0, 0))
+        sv.set_solids(xyz, ub, area, gain)
+        sv.init_equilibrium(rho, u)
+        sv.step(steps)
+        r, uu = (t.cpu().double().numpy() for t in sv.macros())
+        res[storage] = {"u_rel_l2": rel(uu, u_ref), "rho_rel_l2": rel(r, r_ref),
+                        "force_rel": rel(sv.ib_force(), F_ref)}
+        del sv
+    torch.cuda.empty_cache()
+    out["immersed_dense"] = {"case": f"70x18x16 channel, {m} samples (sphere ~44 per base cell, cluster ~375 per "
+                                     f"cell), nu=1e-3, {steps} steps", **res}
+    out["note"] = "the gate of the 16-bit forms is u rel-L2 <= 1e-3 in these terms; FP32 <= 1e-5"
     return out
 
 
@@ -265,7 +460,8 @@ def main():
     ap.add_argument("--storage", default="f32", help="population storage of --profile-pass")
     ap.add_argument("--profile-pass", action="store_true",
                     help="profiler pass: the workload only, then 3 state copies of known size (calibration)")
-    ap.add_argument("--workload", default="turbulence", choices=["turbulence", "sphere", "city", "moving_torus", "adjoint"],
+    ap.add_argument("--workload", default="turbulence",
+                    choices=["turbulence", "sphere", "sphere_dense", "city", "moving_torus", "adjoint"],
                     help="workload of --profile-pass")
     args = ap.parse_args()
 
@@ -282,6 +478,9 @@ def main():
 
     if args.profile_pass and args.workload == "sphere":
         print(json.dumps(sphere_workload(args.steps, args.warmup, args.storage)), flush=True)
+        return
+    if args.profile_pass and args.workload == "sphere_dense":
+        print(json.dumps(dense_sphere_workload(args.steps, args.warmup)), flush=True)
         return
     if args.profile_pass and args.workload == "moving_torus":
         print(json.dumps(moving_torus_workload(args.steps, args.warmup)), flush=True)
@@ -378,12 +577,18 @@ def main():
                 f"vel_rel_l2_vs_f32_gpu_{args.warmup + args.steps}_steps": err,
                 "error_note": "u of this storage form against the FP32 run from the same initial state (the FP32 "
                               "run matches the FP64 oracle to <= 1e-5); the gate's terms are 100 steps"}
+        log("collision models")
+        result["collision_models"] = collision_models(n, rho, u, args.steps, args.warmup)
         log("sphere run")
         result["ib_sphere"] = sphere_workload(min(args.steps, 2000), min(args.warmup, 10))
         result["ib_sphere_f16"] = sphere_workload(min(args.steps, 2000), min(args.warmup, 10), "f16")
+        result["ib_sphere_f16"]["ratio_vs_f32"] = round(result["ib_sphere_f16"]["value"] / result["ib_sphere"]["value"], 3)
+        log("dense sphere run")
+        result["ib_sphere_dense"] = dense_sphere_workload(min(args.steps, 2000), min(args.warmup, 10))
         for storage in ("f32", "f16"):
             log(f"city run {storage}")
             result[f"city_{storage}"] = city_workload(min(args.steps, 100), min(args.warmup, 5), storage)
+        result["city_f16"]["ratio_vs_f32"] = round(result["city_f16"]["value"] / result["city_f32"]["value"], 3)
         log("moving torus run")
         result["moving_torus"] = moving_torus_workload(min(args.steps, 300), min(args.warmup, 10))
         log("adjoint run")
@@ -392,6 +597,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(rho, u, n)
+        if not args.no_extras:
+            log("errors against the FP64 oracle (cpu baseline leg)")
+            result["errors_vs_fp64_oracle"] = oracle_errors()
     print(json.dumps(result), flush=True)
 
 

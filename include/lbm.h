@@ -54,7 +54,12 @@ typedef enum {
 
 /* Domain faces, order -x, +x, -y, +y, -z, +z (Sec. 4.3.3: the domain boundary
  * is treated by bounce-back, Alg. 1).  Readings of the face types:
- *  NOSLIP   halfway bounce-back: f*_i(x) = f_opp(i)(x)           (Alg. 1)
+ *  NOSLIP   halfway bounce-back: f*_i(x) = f_opp(i)(x), the opposite
+ *           population of the same node as it left the collision.  Alg. 1
+ *           prints the copy of the opposite population after streaming,
+ *           f*_opp(i)(x); this library takes the traditional scheme that
+ *           Sec. 4.3.3 names instead (post-collision value), which keeps the
+ *           mass that meets the wall and puts the wall halfway between nodes
  *  INLET    (face -x only) bounce-back with the wall velocity of the inflow:
  *           f*_i(x) = f_opp(i)(x) + 2 w_i rho_w (c_i . u_in(y,z)) / cs^2,
  *           rho_w = 1, cs^2 = 1/3
@@ -118,13 +123,17 @@ lbm_status lbm_workspace_size(const lbm_params *p, size_t *bytes);
  * pull (default: FP32 rows that fill one workgroup with periodic x),
  * LBM_CM_GENERAL = 1 keeps the general central-moment collision when the
  * orders 3 to 6 have unit rates (by default a form specialised to unit rates
- * runs, which needs the forward transform only up to order 2).  Keep them
- * unchanged between the two calls. */
+ * runs, which needs the forward transform only up to order 2),
+ * LBM_IB_LANE_PER_RUN = 1 sums the spreading terms of the samples of one
+ * cell in one lane instead of the default wavefront scan over one lane per
+ * sample (results equal up to FP32 round-off).  Keep them unchanged between
+ * the two calls. */
 lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out);
 
 lbm_status lbm_set_stream(lbm_ctx *ctx, void *hip_stream);
 
-/* Equilibrium initialisation f_i = f_eq_i(rho, u) (product form
+/* Equilibrium initialisation f_i = f_eq_i(rho, u).  The paper fixes no
+ * initial state; this library's reading is the product form
  * rho prod_a phi_{c_ia}(u_a), phi_0 = 2/3 - u^2, phi_{+-1} = (1/3 +- u + u^2)/2,
  * whose central moments are those of the Maxwellian).  rho: device real[N],
  * u: device real[3][N].  Async. */
@@ -203,7 +212,8 @@ lbm_status lbm_macros(lbm_ctx *ctx, void *rho, void *u);
 lbm_status lbm_conserved(lbm_ctx *ctx, double out[4]);
 
 /* FP64 total sum_s a_s g_s of the penalty force applied in the last step
- * (force on the fluid; drag on the solid is its negative).  Sync. */
+ * (Alg. 2 (c), total force; Eqs. 7-8 with the area weights): the force on
+ * the fluid, so the drag on the solid is its negative.  Sync. */
 lbm_status lbm_ib_force(lbm_ctx *ctx, double out[3]);
 
 /* FP64 total torque sum_s (x_s - o) x (a_s g_s) of the penalty forces applied

@@ -226,6 +226,16 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, voi
         const bool force_ptr = e && std::strtol(e, nullptr, 10) != 0;
         c->buffer_path = !force_ptr && p->storage != LBM_F64 &&
                          (uint64_t)Q * (uint64_t)L.plane * L.esize < (uint64_t(1) << 31);
+        // interior loads by 32-bit offsets from each wavefront's lowest source
+        // row (blocked layout): rows (z-1, y-1) .. (z+1, y+1) span 2 ny + 3
+        // rows, i.e. at most (2 ny + 2) / R + 2 blocks, which must stay below
+        // 2^31 bytes (LBM_BUF_LOADS=0 keeps pointer loads)
+        const char *bl = std::getenv("LBM_BUF_LOADS");
+        const uint64_t rpb = uint64_t(1) << (L.lr < 31 ? L.lr : 0);
+        const uint64_t span = ((2 * (uint64_t)p->ny + 2) / rpb + 2) * (uint64_t)L.bstride * L.esize;
+        c->load32 = c->buffer_path && L.lr < 31 && !(bl && std::strtol(bl, nullptr, 10) == 0) &&
+                    span < (uint64_t(1) << 31);
+        c->span32 = c->load32 ? (uint32_t)span : 0u;
         // LDS row staging: one workgroup per row, periodic x, FP32 storage (measured at 256^3:
         // 0.6% faster in FP32, 5.6% slower in the ALU-bound 16-bit forms); LBM_ROW_STAGE=0
         // disables it, =1 also enables it for 16-bit storage (measurements and tests)
@@ -243,6 +253,10 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, voi
                   : p->collision == LBM_RMMRT ? COLL_RM
                   : (unit_high && !general)   ? COLL_CM_UNIT_HIGH
                                               : COLL_CM;
+        // spreading sums: wavefront scan, one lane per sample (default), or
+        // one lane per run with LBM_IB_LANE_PER_RUN=1 (for measurements)
+        const char *ib = std::getenv("LBM_IB_LANE_PER_RUN");
+        c->ib_lane_per_run = ib && std::strtol(ib, nullptr, 10) != 0;
     }
     c->ws = static_cast<char *>(workspace);
     c->ws_bytes = ws_bytes;

@@ -377,18 +377,26 @@ __global__ void k_mk_slots(MarkerGeom mg, int64_t n, const float *__restrict__ p
 }
 
 // runs of sorted samples that share a base cell (slot of stencil offset 0)
+// A run starts where the base cell changes (slot of stencil offset 0) and at
+// every multiple of 64 sorted samples (the window of one spreading wavefront).
 __global__ void k_run_heads(int64_t n, const int32_t *__restrict__ slot0, int32_t *__restrict__ head)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) head[k] = (k == 0 || slot0[k] != slot0[k - 1]) ? 1 : 0;
+    if (k < n) head[k] = ((k & 63) == 0 || slot0[k] != slot0[k - 1]) ? 1 : 0;
 }
 
+// run starts, and whether a run continues the cell of the run before it
+// (cut at a window boundary only)
 __global__ void k_run_start(int64_t n, const int32_t *__restrict__ head, const int32_t *__restrict__ run_id,
-                            int32_t *__restrict__ run_start)
+                            const int32_t *__restrict__ slot0, int32_t *__restrict__ run_start,
+                            uint8_t *__restrict__ run_cont)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    if (head[k]) run_start[run_id[k]] = (int32_t)k;
+    if (head[k]) {
+        run_start[run_id[k]] = (int32_t)k;
+        run_cont[run_id[k]] = (k > 0 && slot0[k] == slot0[k - 1]) ? 1 : 0;
+    }
     if (k == n - 1) run_start[run_id[k] + head[k]] = (int32_t)n;
 }
 
@@ -420,12 +428,14 @@ __global__ void k_clear_band_src(int32_t *__restrict__ band_src, const int32_t *
         band_src[k] = -1;
 }
 
+// band_src[d][j] = the first run of the cell whose stencil offset d is band node j
 __global__ void k_band_src(int64_t n, const int32_t *__restrict__ counts, const int32_t *__restrict__ run_start,
-                           const int32_t *__restrict__ slot, int32_t *__restrict__ band_src)
+                           const uint8_t *__restrict__ run_cont, const int32_t *__restrict__ slot,
+                           int32_t *__restrict__ band_src)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nband = counts[0], nruns = counts[1];
-    if (r >= nruns) return;
+    if (r >= nruns || run_cont[r]) return;
     const int64_t k0 = run_start[r];
     for (int d = 0; d < 8; ++d) band_src[(int64_t)d * nband + slot[(int64_t)d * n + k0]] = (int32_t)r;
 }
@@ -505,7 +515,6 @@ hipError_t launch_set_pop(lbm_ctx *c, const void *f) { LBM_DISPATCH(set_pop_st, 
 hipError_t launch_get_pop(lbm_ctx *c, void *f) { LBM_DISPATCH(get_pop_st, c, f) }
 hipError_t launch_macros(lbm_ctx *c, void *rho, void *u) { LBM_DISPATCH(macros_st, c, rho, u) }
 hipError_t launch_conserved(lbm_ctx *c) { LBM_DISPATCH(conserved_st, c) }
-
 hipError_t launch_copy(lbm_ctx *c, void *dst, const void *src, size_t bytes)
 {
     const int64_t n16 = (int64_t)(bytes / 16), tail = (int64_t)(bytes % 16);
@@ -618,6 +627,7 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
     L->run_head = take(un * 4);
     L->run_id = take(un * 4);
     L->run_start = take((un + 1) * 4);
+    L->run_cont = take(un);
     L->run_sum = take(8 * un * 4 * c->rsize);
     L->band_src = take(8 * nbmax * 4);
     L->cell2 = take(un * 4);
@@ -694,16 +704,19 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
     int32_t *head = reinterpret_cast<int32_t *>(m + L.run_head);
     int32_t *rid = reinterpret_cast<int32_t *>(m + L.run_id);
     c->run_start = reinterpret_cast<int32_t *>(m + L.run_start);
+    c->run_id = rid;
+    c->run_cont = reinterpret_cast<uint8_t *>(m + L.run_cont);
     c->run_sum = m + L.run_sum;
     c->band_src = reinterpret_cast<int32_t *>(m + L.band_src);
     hipLaunchKernelGGL(k_run_heads, grid_for(n), dim3(256), 0, st, n, c->m_slot, head);
     scan_bytes = L.scan_tmp_bytes;
     e = hipcub::DeviceScan::ExclusiveSum(m + L.scan_tmp, scan_bytes, head, rid, (int)n, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_run_start, grid_for(n), dim3(256), 0, st, n, head, rid, c->run_start);
+    hipLaunchKernelGGL(k_run_start, grid_for(n), dim3(256), 0, st, n, head, rid, c->m_slot, c->run_start, c->run_cont);
     hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, st, c->g.W, c->tile_start, cnt, n, rid, head, counts);
     hipLaunchKernelGGL(k_clear_band_src, dim3(1024), dim3(256), 0, st, c->band_src, counts);
-    hipLaunchKernelGGL(k_band_src, grid_for(n), dim3(256), 0, st, n, counts, c->run_start, c->m_slot, c->band_src);
+    hipLaunchKernelGGL(k_band_src, grid_for(n), dim3(256), 0, st, n, counts, c->run_start, c->run_cont, c->m_slot,
+                       c->band_src);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int32_t got[2];
     if ((e = hipMemcpyAsync(got, counts, sizeof(got), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;

@@ -20,6 +20,8 @@ struct lbm_ctx {
     size_t esize = 4;      // bytes per stored population
     size_t rsize = 4;      // bytes of the arithmetic type
     bool buffer_path = false;  // fused kernel stores through per-row buffer descriptors
+    bool load32 = false;       // with buffer_path: interior loads by 32-bit offsets from a per-wave base
+    uint32_t span32 = 0;       // bytes that cover the 9 source rows from the lowest one
     bool row_stage = false;    // fused kernel stages whole rows in LDS (segments per row == waves per block, periodic x)
     int coll = 0;              // collision variant of the fused kernel (COLL_* of lbm_internal.hpp)
     // caller workspace
@@ -54,8 +56,11 @@ struct lbm_ctx {
     void *band_ru = nullptr;       // [nband] real4 (rho, u)
     void *band_force = nullptr;    // [nband] real4 (g, 0)
     double *ib_part = nullptr;     // [ceil(nruns/256)][8] per-block force and torque partials
-    int64_t nruns = 0;             // runs of samples sharing a base cell (sorted order)
+    int64_t nruns = 0;             // runs: samples of one base cell, cut at every 64 sorted samples
     int32_t *run_start = nullptr;  // [nruns + 1] first sorted sample of each run
+    int32_t *run_id = nullptr;     // [nm] run of each sorted sample
+    uint8_t *run_cont = nullptr;   // [nruns] 1 if the run continues the cell of the run before it
+    bool ib_lane_per_run = false;  // spreading sums by one lane per run instead of the wavefront scan
     void *run_sum = nullptr;       // [8][nruns] real4: a K_d g summed over the run, per stencil offset d
     int32_t *band_src = nullptr;   // [8][nband] run feeding band node j through offset d, or -1
     // adjoint workspace (caller-owned)
@@ -74,7 +79,7 @@ namespace lbm {
 struct SolidsLayout {
     size_t pos, ub, area, gain, slot, cell, perm, keys_in, keys_out, idx_in, sort_tmp, sort_tmp_bytes;
     size_t tile_mask, tile_start, tile_count, scan_tmp, scan_tmp_bytes, band_cell, band_ru, band_force, ib_part, misc;
-    size_t run_head, run_id, run_start, run_sum, band_src;
+    size_t run_head, run_id, run_start, run_cont, run_sum, band_src;
     size_t cell2, body_xyz, body_ub, body_area, body_gain, world_xyz, world_ub;
     size_t total;
 };

@@ -243,6 +243,15 @@ __device__ __forceinline__ BufRsrc make_rsrc(const void *base, uint32_t bytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
+template <typename T> __device__ __forceinline__ T buf_ld(BufRsrc r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float buf_ld<float>(BufRsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ uint16_t buf_ld<uint16_t>(BufRsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+}
 // non-temporal store (aux bit 1 = nt)
 template <typename T> __device__ __forceinline__ void buf_st_nt(T v, BufRsrc r, uint32_t voff, uint32_t soff);
 template <> __device__ __forceinline__ void buf_st_nt<float>(float v, BufRsrc r, uint32_t voff, uint32_t soff)
@@ -404,6 +413,42 @@ __device__ __forceinline__ void pull_interior(R (&f)[3][3][3], const typename St
     }
 }
 
+// Interior pull with 32-bit offsets, for a row (y, z) away from every y and
+// z face or wrap (1 <= y <= ny-2, 1 <= z <= nz-2): one buffer descriptor per
+// wavefront based at its lowest source row (z-1, y-1), spanning `span`
+// bytes; the (population, source row) part of each offset in a scalar
+// register and the lane's source x in one of three vector registers (x - 1,
+// x, x + 1, wrapped), so the 27 loads need no 64-bit address arithmetic,
+// scalar or vector.  The host guarantees that the 9 source rows of any such
+// row lie within `span` < 2^31 bytes of the base (blocked layout only).
+template <int ST, typename R>
+__device__ __forceinline__ void pull_interior32(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int x,
+                                                int y, int z, const Geom &g, uint32_t span)
+{
+    using T = typename Store<ST>::T;
+    const int row0 = (z - 1) * g.ny + (y - 1);
+    const BufRsrc rs = make_rsrc(in + row_off(g, row0), span);
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const uint32_t xb[3] = {(uint32_t)(xp * (int)sizeof(T)), (uint32_t)(x * (int)sizeof(T)),
+                            (uint32_t)(xm * (int)sizeof(T))};  // source x for c_x = -1, 0, +1
+    const int lr = g.lr, rmask = (int)g.rmask, nxp = g.nxp, bstride = (int)g.bstride;
+    const int hi0 = row0 >> lr, lo0 = row0 & rmask;
+    const uint32_t plane_b = (uint32_t)g.plane * (uint32_t)sizeof(T);
+    uint32_t rb[3][3];  // byte offset of source row (y + 1 - b, z + 1 - a) from the base
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int row = row0 + (2 - a) * g.ny + (2 - b);
+            const int el = ((row >> lr) - hi0) * bstride + ((row & rmask) - lo0) * nxp;
+            rb[a][b] = (uint32_t)el * (uint32_t)sizeof(T);
+        }
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] =
+            Store<ST>::dec(buf_ld<T>(rs, xb[CX[i] + 1], rb[CZ[i] + 1][CY[i] + 1] + (uint32_t)i * plane_b));
+}
+
 // Pull for a wave that touches a non-periodic x face but no y or z face (an
 // x-segment at either end of a row).  Directions with c_x = 0 read as in the
 // interior.  The others select per lane between the plain source and the face
@@ -463,6 +508,20 @@ __device__ __forceinline__ void pull_wave(R (&f)[3][3][3], const typename Store<
     if (yz) pull_general<ST>(f, in, x, y, z, g, inl);
     else if (xf) pull_xface<ST>(f, in, x, y, z, g, inl);
     else pull_interior<ST>(f, in, x, y, z, g);
+}
+// the same with the 32-bit interior pull on rows away from y and z faces and wraps
+template <int ST, typename R>
+__device__ __forceinline__ void pull_wave32(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int xs,
+                                            int x, int y, int z, const Geom &g, const Inlet<R> &inl, uint32_t span)
+{
+    const bool yz = (y == 0 && g.face[2] != LBM_PERIODIC) || (y == g.ny - 1 && g.face[3] != LBM_PERIODIC) ||
+                    (z == 0 && g.face[4] != LBM_PERIODIC) || (z == g.nz - 1 && g.face[5] != LBM_PERIODIC);
+    const bool xf = (xs == 0 && g.face[0] != LBM_PERIODIC) || (xs == g.ntx - 1 && g.face[1] != LBM_PERIODIC);
+    const bool wrap = y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1;
+    if (yz) pull_general<ST>(f, in, x, y, z, g, inl);
+    else if (xf) pull_xface<ST>(f, in, x, y, z, g, inl);
+    else if (wrap) pull_interior<ST>(f, in, x, y, z, g);
+    else pull_interior32<ST>(f, in, x, y, z, g, span);
 }
 
 

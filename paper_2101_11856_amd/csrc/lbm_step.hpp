@@ -36,6 +36,8 @@ template <int ST> struct StepParams {
     const float *__restrict__ sc_in;
     float *__restrict__ sc_out;
     int sc_h;
+    int load32;     // interior loads by 32-bit offsets from a per-wavefront base (blocked layout)
+    uint32_t span;  // bytes from a row's lowest source row that cover its 9 source rows
 };
 
 // ---------------------------------------------------------------------------
@@ -115,9 +117,28 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
             const int ysrc[3] = {yp, y, ym};
             const int zsrc[3] = {zp, z, zm};
             if (active) {
+                if (P.load32 && y > 0 && y < g.ny - 1 && z > 0 && z < g.nz - 1) {
+                    // 32-bit offsets from the lowest source row (see pull_interior32)
+                    const int row0 = (z - 1) * g.ny + (y - 1);
+                    const BufRsrc rs = make_rsrc(P.fin + row_off(g, row0), P.span);
+                    const int lr = g.lr, rmask = (int)g.rmask, hi0 = row0 >> lr, lo0 = row0 & rmask;
+                    uint32_t rb[3][3];
 #pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    row[i][x] = P.fin[(int64_t)i * g.plane + row_off(g, ysrc[CY[i] + 1], zsrc[CZ[i] + 1]) + x];
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            const int rw = row0 + (2 - a) * g.ny + (2 - b);
+                            const int el = ((rw >> lr) - hi0) * (int)g.bstride + ((rw & rmask) - lo0) * g.nxp;
+                            rb[a][b] = (uint32_t)el * (uint32_t)sizeof(T);
+                        }
+                    const uint32_t plane_b = (uint32_t)g.plane * (uint32_t)sizeof(T), xb = (uint32_t)(x * sizeof(T));
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) row[i][x] = buf_ld<T>(rs, xb, rb[CZ[i] + 1][CY[i] + 1] + (uint32_t)i * plane_b);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i)
+                        row[i][x] = P.fin[(int64_t)i * g.plane + row_off(g, ysrc[CY[i] + 1], zsrc[CZ[i] + 1]) + x];
+                }
             }
             __syncthreads();
             const int xm = xc == 0 ? g.nx - 1 : xc - 1, xp = xc == g.nx - 1 ? 0 : xc + 1;
@@ -125,6 +146,8 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
 #pragma unroll
             for (int i = 0; i < Q; ++i) f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(row[i][xsrc[CX[i] + 1]]);
         }
+    } else if (B32 && P.load32) {
+        pull_wave32<ST>(f, P.fin, xs, xc, y, z, g, P.inlet, P.span);
     } else {
         pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
     }
@@ -188,19 +211,30 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// immersed boundary (Eqs. 6-8), spreading in two deterministic phases
-//   k_ib_run: one lane per run of sorted samples sharing a base cell (the
-//     samples of one cell are contiguous, Sec. 4.2.2 order).  The run's 8
-//     stencil nodes and their (rho, u0) are loaded once; each sample adds
-//     a_s K_d g_s to a register accumulator per offset d; the run stores its
-//     8 sums (no atomics).
-//   k_spread: one lane per band node gathers the (at most 8) run sums that
-//     target it, in a fixed order.
+// immersed boundary (Eqs. 6-8), spreading in two deterministic phases.  The
+// samples of one base cell are contiguous in the sorted order (Sec. 4.2.2);
+// a "run" is such a group cut at every multiple of 64 sorted samples, so
+// that no run leaves the 64-sample window of one wavefront.  A cell whose
+// samples straddle a window boundary has two runs; the second is marked as
+// continuing the first (run_cont).
+//   k_ib_seg (default): one lane per sample.  Each lane interpolates (Eq. 6),
+//     forms its penalty force (Eq. 7) and its 24 spreading terms
+//     a_s K_d g_s (8 offsets d x 3 components); a segmented inclusive scan
+//     across the wavefront sums them per run (the wavefront-level reduction
+//     that replaces the paper's atomics), and the last lane of each run
+//     stores the run's 8 sums.  Work per lane is the same for every sample,
+//     however the samples are spread over cells (Sec. 4.3, Table 1).
+//   k_ib_run: one lane per run, looping over the run's samples with the 8
+//     stencil nodes loaded once (the lane's time grows with its run length).
+//   k_spread: one lane per band node gathers, per offset, the sums of the
+//     run(s) of the cell that targets it, in a fixed order.
+// No floating-point atomics anywhere: the step is bit-reproducible.
 // ---------------------------------------------------------------------------
 template <typename R> struct IbParams {
     using R4 = typename R4T<R>::type;
     int64_t n, nruns, nband;
     const int32_t *__restrict__ run_start;  // [nruns + 1]
+    const int32_t *__restrict__ run_id;     // [n] run of each sorted sample
     const float *__restrict__ pos;          // [3][n] sorted
     const float *__restrict__ ub;           // [3][n]
     const float *__restrict__ area;         // [n]
@@ -212,12 +246,30 @@ template <typename R> struct IbParams {
     double ox, oy, oz;                      // reference point of the torque
 };
 
+// FP64 force and torque of the block's lanes into one partial per block
+// (wave reduction, then the block's waves in order; no same-address atomics)
+__device__ __forceinline__ void block_partial6(double (&tot)[6], double *__restrict__ part)
+{
+    __shared__ double wsum[4][6];
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) tot[a] += __shfl_down(tot[a], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) wsum[threadIdx.x >> 6][a] = tot[a];
+    __syncthreads();
+    if (threadIdx.x < 6)
+        part[8 * blockIdx.x + threadIdx.x] =
+            wsum[0][threadIdx.x] + wsum[1][threadIdx.x] + wsum[2][threadIdx.x] + wsum[3][threadIdx.x];
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_ib_run(const IbParams<R> P)
 {
     using R4 = typename R4T<R>::type;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
     const int64_t n = P.n;
     double tot[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // force, then torque about (ox, oy, oz)
     if (r < P.nruns) {
@@ -273,24 +325,101 @@ __global__ void __launch_bounds__(256) k_ib_run(const IbParams<R> P)
             P.run_sum[(int64_t)d * P.nruns + r] = v;
         }
     }
-    // FP64 total force and torque: wave reduction, then one partial per block
-    // (no same-address atomics; the partials are summed in order afterwards)
-    __shared__ double wsum[4][6];
+    block_partial6(tot, P.part);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_ib_seg(const IbParams<R> P)
+{
+    using R4 = typename R4T<R>::type;
+    const int64_t n = P.n;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;  // == k mod 64: runs restart at every window
+    const bool valid = k < n;
+    const int32_t c0 = valid ? P.slot[k] : -1;  // band slot of the base cell (offset 0) names the cell
+    const int32_t cprev = __shfl_up(c0, 1, 64);
+    const bool head = valid && (lane == 0 || c0 != cprev);
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const uint64_t hle = heads & upto;
+    const int first = hle ? 63 - __clzll(hle) : lane;   // first lane of this lane's run
+    const int dist = valid ? lane - first : 0;
+    const bool last = valid && (lane == 63 || k + 1 == n || ((heads >> (lane + 1)) & 1ull));
+
+    R v[8][3];
+    double tot[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // force, then torque about (ox, oy, oz)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
+    for (int d = 0; d < 8; ++d) v[d][0] = v[d][1] = v[d][2] = (R)0;
+    if (valid) {
+        R t[3];
+        float p[3];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) tot[a] += __shfl_down(tot[a], off, 64);
-    if (lane == 0)
+        for (int a = 0; a < 3; ++a) {
+            p[a] = P.pos[a * n + k];
+            t[a] = (R)(p[a] - floorf(p[a]));
+        }
+        R K[8], rs = 0, us[3] = {0, 0, 0};
 #pragma unroll
-        for (int a = 0; a < 6; ++a) wsum[threadIdx.x >> 6][a] = tot[a];
-    __syncthreads();
-    if (threadIdx.x < 6)
-        P.part[8 * blockIdx.x + threadIdx.x] =
-            wsum[0][threadIdx.x] + wsum[1][threadIdx.x] + wsum[2][threadIdx.x] + wsum[3][threadIdx.x];
+        for (int d = 0; d < 8; ++d) {
+            const R4 node = P.band_ru[P.slot[(int64_t)d * n + k]];
+            K[d] = ((d & 1) ? t[0] : (R)1 - t[0]) * ((d & 2) ? t[1] : (R)1 - t[1]) * ((d & 4) ? t[2] : (R)1 - t[2]);
+            rs += K[d] * node.x;
+            us[0] += K[d] * node.y;
+            us[1] += K[d] * node.z;
+            us[2] += K[d] * node.w;
+        }
+        // Eq. (7) with the sample's gain; Eq. (8) carries the area weight
+        const R ag = (R)P.area[k] * (R)P.gain[k] * rs;
+        R aG[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            aG[a] = ag * ((R)P.ub[a * n + k] - us[a]);
+            tot[a] = (double)aG[a];
+        }
+        // Alg. 2 (c) torque: (x_s - o) x (a_s g_s), lever arm in FP64
+        const double rx = (double)p[0] - P.ox, ry = (double)p[1] - P.oy, rz = (double)p[2] - P.oz;
+        tot[3] = ry * (double)aG[2] - rz * (double)aG[1];
+        tot[4] = rz * (double)aG[0] - rx * (double)aG[2];
+        tot[5] = rx * (double)aG[1] - ry * (double)aG[0];
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v[d][a] = K[d] * aG[a];
+    }
+    // segmented inclusive scan: after the steps with offsets 1, 2, 4, ... up
+    // to the longest run, the last lane of a run holds the run's sums (a
+    // fixed tree order, so repeated runs give the same bits)
+    int span = dist;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) span = max(span, __shfl_xor(span, off, 64));
+    span = __builtin_amdgcn_readfirstlane(span);
+    for (int off = 1; off <= span; off <<= 1) {
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R up = __shfl_up(v[d][a], off, 64);
+                if (dist >= off) v[d][a] += up;
+            }
+    }
+    if (last) {
+        const int64_t r = (int64_t)P.run_id[k - lane] + (int64_t)__popcll(hle) - 1;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            R4 w;
+            w.x = v[d][0];
+            w.y = v[d][1];
+            w.z = v[d][2];
+            w.w = (R)0;
+            P.run_sum[(int64_t)d * P.nruns + r] = w;
+        }
+    }
+    block_partial6(tot, P.part);
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_spread(int64_t nband, int64_t nruns, const int32_t *__restrict__ band_src,
+                                                const uint8_t *__restrict__ run_cont,
                                                 const typename R4T<R>::type *__restrict__ run_sum,
                                                 typename R4T<R>::type *__restrict__ band_force)
 {
@@ -300,12 +429,17 @@ __global__ void __launch_bounds__(256) k_spread(int64_t nband, int64_t nruns, co
     g.x = g.y = g.z = g.w = (R)0;
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
-        const int32_t src = band_src[(int64_t)d * nband + j];
+        int64_t src = band_src[(int64_t)d * nband + j];
         if (src >= 0) {
-            const auto v = run_sum[(int64_t)d * nruns + src];
-            g.x += v.x;
-            g.y += v.y;
-            g.z += v.z;
+            // the first run of the cell, then any runs continuing it
+            for (;;) {
+                const auto v = run_sum[(int64_t)d * nruns + src];
+                g.x += v.x;
+                g.y += v.y;
+                g.z += v.z;
+                if (src + 1 >= nruns || !run_cont[src + 1]) break;
+                ++src;
+            }
         }
     }
     band_force[j] = g;
@@ -356,6 +490,8 @@ template <int ST> StepParams<ST> make_params(lbm_ctx *c)
     P.sc_in = c->scA;
     P.sc_out = c->scB;
     P.sc_h = c->p.scalar_inlet_height;
+    P.load32 = c->load32 ? 1 : 0;
+    P.span = c->span32;
     return P;
 }
 
@@ -400,6 +536,7 @@ template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *f
     Q.nruns = c->nruns;
     Q.nband = c->nband;
     Q.run_start = c->run_start;
+    Q.run_id = c->run_id;
     Q.pos = c->m_pos;
     Q.ub = c->m_ub;
     Q.area = c->m_area;
@@ -411,11 +548,13 @@ template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *f
     Q.ox = c->pose_o[0];
     Q.oy = c->pose_o[1];
     Q.oz = c->pose_o[2];
-    const int nblk = (int)((c->nruns + 255) / 256);
-    hipLaunchKernelGGL((k_ib_run<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
+    const int nblk = (int)(((c->ib_lane_per_run ? c->nruns : c->nm) + 255) / 256);
+    if (c->ib_lane_per_run) hipLaunchKernelGGL((k_ib_run<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
+    else hipLaunchKernelGGL((k_ib_seg<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
     hipLaunchKernelGGL(k_ib_total<>, dim3(1), dim3(256), 0, c->stream, c->ib_part, nblk, ftot);
     hipLaunchKernelGGL((k_spread<R>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, c->nband, c->nruns,
-                       c->band_src, static_cast<const R4 *>(c->run_sum), static_cast<R4 *>(c->band_force));
+                       c->band_src, c->run_cont, static_cast<const R4 *>(c->run_sum),
+                       static_cast<R4 *>(c->band_force));
     return hipGetLastError();
 }
 

@@ -206,6 +206,68 @@ def test_ib_steps(name, shape, faces, storage):
     assert e_u <= gate and e_r <= gate and e_F <= (1e-11 if storage == "f64" else 1e-4)
 
 
+def _dense_scene(nx, ny, nz, seed):
+    """The paper's sampling density (Sec. 3.1: 10-100 samples per cell near
+    the boundary): a sphere of R = 5 with 20,000 samples (about 44 per base
+    cell, up to 87), plus 3,000 samples packed into 8 cells (about 375 per
+    cell, so one cell's samples span several 64-sample spreading windows)."""
+    rng = np.random.default_rng(seed)
+    sph = synth.fibonacci_sphere(20000, 5.0, (14.3, ny / 2 + 0.2, nz / 2 - 0.1))
+    clu = synth.random_box(3000, (40.0, 8.0, 7.0), (42.0, 10.0, 9.0), seed + 1)
+    xyz = np.concatenate([sph, clu], axis=1)
+    n = xyz.shape[1]
+    ub = (0.01 * rng.standard_normal((3, n))).astype(np.float32)
+    area = np.concatenate([np.full(20000, 4 * np.pi * 25.0 / 20000), np.full(3000, 8.0 / 3000)])
+    area = (area * (0.7 + 0.6 * rng.random(n))).astype(np.float32)
+    gain = (0.5 + rng.random(n)).astype(np.float32)
+    return xyz, ub, area, gain
+
+
+@pytest.mark.parametrize("mode", ["wave-scan", "lane-per-run"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_ib_dense_sampling(storage, mode, monkeypatch):
+    """Both spreading-sum kernels at the paper's sampling density against the
+    oracle: maps bit-exact, 10 steps, force; repeated runs bit-identical."""
+    nx, ny, nz = 70, 18, 16
+    faces = (IN, OUT, NS, FS, P, P)
+    say(f"ib dense sampling {storage} {mode}")
+    if mode == "lane-per-run":
+        monkeypatch.setenv("LBM_IB_LANE_PER_RUN", "1")
+    else:
+        monkeypatch.delenv("LBM_IB_LANE_PER_RUN", raising=False)
+    xyz, ub, area, gain = _dense_scene(nx, ny, nz, 31)
+    rng = np.random.default_rng(32)
+    rho = (1.0 + 1e-3 * rng.standard_normal((nz, ny, nx))).astype(np.float32)
+    u = np.zeros((3, nz, ny, nx), np.float32)
+    u[0] = 0.03
+    u += (0.005 * rng.standard_normal(u.shape)).astype(np.float32)
+    steps = 10
+    S = O.OracleSim(nx, ny, nz, 0.05, faces=faces, u_in=(0.03, 0, 0))
+    S.set_markers(xyz, ub.astype(np.float64), area.astype(np.float64), gain.astype(np.float64))
+    fl_ref, cell_ref, perm_ref = S.maps()
+    S.init_equilibrium(rho.astype(np.float64), u.astype(np.float64))
+    S.step(steps)
+    r_ref, u_ref = S.macros()
+    F_ref = S.last_force()
+    real = np.float64 if storage == "f64" else np.float32
+    out = []
+    for _rep in range(2):
+        s = gpu_solver(nx, ny, nz, 0.05, storage=storage, faces=faces, u_in=(0.03, 0, 0))
+        s.set_solids(xyz, ub, area, gain)
+        fl, cell, perm = (t.cpu().numpy() for t in s.solid_maps())
+        assert np.array_equal(cell, cell_ref) and np.array_equal(perm, perm_ref) and np.array_equal(fl, fl_ref)
+        s.init_equilibrium(rho.astype(real), u.astype(real))
+        s.step(steps)
+        out.append((s.checkpoint().clone(), s.ib_force()))
+        r, uu = (to_np(t) for t in s.macros())
+        F = s.ib_force()
+        e_u, e_r, e_F = rel_l2(uu, u_ref), rel_l2(r, r_ref), rel_l2(F, F_ref)
+        say(f"  rel-L2 u={e_u:.3e} rho={e_r:.3e} force={e_F:.3e}")
+        gate = 1e-12 if storage == "f64" else FP32_GATE
+        assert e_u <= gate and e_r <= gate and e_F <= (1e-11 if storage == "f64" else 1e-4)
+    assert torch.equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 def test_ib_force_eval_matches_oracle():
     nx, ny, nz = 70, 18, 16
     say("ib force eval")
