@@ -10,7 +10,8 @@
  *  - The library never allocates device memory: the caller passes one device
  *    workspace at create time (size from lbm_workspace_size) and one for the
  *    solid samples (size from lbm_solids_ws_size).  Both stay owned by the
- *    caller and must outlive the context.
+ *    caller and must outlive the context.  The one device memory of the
+ *    library's own is a static 64 KiB array per GPU (lbm_conserved_static).
  *  - All work is enqueued on the caller's HIP stream given to lbm_create (or
  *    lbm_set_stream).  Calls marked "sync" wait for that stream; all others are
  *    asynchronous and return after enqueueing.
@@ -210,6 +211,20 @@ lbm_status lbm_macros(lbm_ctx *ctx, void *rho, void *u);
  * sum c_z f} (Eq. 1 conserves them).  Returns LBM_E_NONFINITE if any stored
  * value is NaN or Inf.  Sync. */
 lbm_status lbm_conserved(lbm_ctx *ctx, double out[4]);
+
+/* lbm_conserved for callers that cannot allocate device memory at all (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same totals and the same LBM_E_NONFINITE check, computed
+ * by the same kernels, but the per-block partial sums, the non-finite counter
+ * and the totals live in a library-owned static device array of 64 KiB per
+ * GPU (held until the process ends) instead of the context's workspace.  It
+ * allocates nothing and calls no allocating routine.  The array of one GPU is
+ * shared by every context and stream on it and keeps the last call's
+ * contents (the counter is cleared by a kernel at every call), so calls that
+ * overlap on one GPU race.  A context whose reduction needs more than the
+ * array holds (at most 1024 per-block partials are used, so no valid grid
+ * does) gets LBM_E_INVAL.  out: host double[4].  Sync. */
+lbm_status lbm_conserved_static(lbm_ctx *ctx, double out[4]);
 
 /* FP64 total sum_s a_s g_s of the penalty force applied in the last step
  * (Alg. 2 (c), total force; Eqs. 7-8 with the area weights): the force on

@@ -111,7 +111,7 @@ Layout layout(const lbm_params *p)
     L.esize = p->storage == LBM_F32 ? 4 : p->storage == LBM_F64 ? 8 : 2;
     L.rsize = p->storage == LBM_F64 ? 8 : 4;
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
-    L.red_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (N + 255) / 256));
+    L.red_blocks = (int)std::min<int64_t>(MAX_RED_BLOCKS, std::max<int64_t>(1, (N + 255) / 256));
     const size_t fbytes = align_up((size_t)L.pop_elems * L.esize, ALIGN);
     const size_t sbytes = p->passive_scalar ? align_up((size_t)L.rows * L.nxp * 4, ALIGN) : 0;
     size_t o = 0;
@@ -482,6 +482,21 @@ lbm_status lbm_conserved(lbm_ctx *c, double out[4])
     HIP_TRY(c, hipMemcpyAsync(out, c->red_out, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "lbm_conserved");
     HIP_TRY(c, hipMemcpyAsync(&flag, c->red_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "lbm_conserved");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "lbm_conserved");
+    if (flag) return fail(c, LBM_E_NONFINITE, "non-finite populations in the state");
+    return LBM_OK;
+}
+
+lbm_status lbm_conserved_static(lbm_ctx *c, double out[4])
+{
+    CHECK_CTX(c);
+    if (!out) return fail(c, LBM_E_INVAL, "out is NULL");
+    const size_t need = conserved_static_need(c);
+    if (need > STATIC_SCRATCH_BYTES)
+        return fail(c, LBM_E_INVAL,
+                    "lbm_conserved_static: the reduction needs " + std::to_string(need) +
+                        " bytes of scratch, more than the static array's " + std::to_string(STATIC_SCRATCH_BYTES));
+    int flag = 0;
+    HIP_TRY(c, launch_conserved_static(c, out, &flag), "lbm_conserved_static");
     if (flag) return fail(c, LBM_E_NONFINITE, "non-finite populations in the state");
     return LBM_OK;
 }

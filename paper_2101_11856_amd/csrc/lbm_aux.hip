@@ -2,6 +2,8 @@
 // reductions, state copies and the set-up of the immersed solid samples.
 #include <hipcub/hipcub.hpp>
 
+#include <mutex>
+
 #include "lbm_ctx.hpp"
 
 namespace lbm {
@@ -491,13 +493,15 @@ template <int ST> static hipError_t macros_st(lbm_ctx *c, void *rho, void *u)
                        c->N);
     return hipGetLastError();
 }
-template <int ST> static hipError_t conserved_st(lbm_ctx *c)
+// the totals into (part [red_blocks][4], flag, out [4]): the context's
+// workspace for lbm_conserved, the static scratch array for
+// lbm_conserved_static
+template <int ST> static hipError_t conserved_st(lbm_ctx *c, double *part, int *flag, double *out)
 {
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c->stream, c->red_flag);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c->stream, flag);
     hipLaunchKernelGGL((k_conserved<ST>), dim3(c->red_blocks), dim3(256), 0, c->stream, c->g,
-                       static_cast<const TT<ST> *>(c->fA), c->N, c->red_part, c->red_flag);
-    hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(64), 0, c->stream, c->red_part, c->red_blocks, (double)c->N,
-                       c->red_out);
+                       static_cast<const TT<ST> *>(c->fA), c->N, part, flag);
+    hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(64), 0, c->stream, part, c->red_blocks, (double)c->N, out);
     return hipGetLastError();
 }
 
@@ -514,7 +518,74 @@ hipError_t launch_init_eq(lbm_ctx *c, const void *rho, const void *u) { LBM_DISP
 hipError_t launch_set_pop(lbm_ctx *c, const void *f) { LBM_DISPATCH(set_pop_st, c, f) }
 hipError_t launch_get_pop(lbm_ctx *c, void *f) { LBM_DISPATCH(get_pop_st, c, f) }
 hipError_t launch_macros(lbm_ctx *c, void *rho, void *u) { LBM_DISPATCH(macros_st, c, rho, u) }
-hipError_t launch_conserved(lbm_ctx *c) { LBM_DISPATCH(conserved_st, c) }
+hipError_t launch_conserved(lbm_ctx *c) { LBM_DISPATCH(conserved_st, c, c->red_part, c->red_flag, c->red_out) }
+
+// ---------------------------------------------------------------------------
+// Library-owned scratch of lbm_conserved_static, for callers that cannot
+// allocate: one array per GPU, held until the process ends.  Layout: the
+// per-block partials [red_blocks][4] doubles from offset 0, the non-finite
+// counter at CONS_FLAG_OFF, the 4 totals at CONS_OUT_OFF.  In host code the
+// name `scratch` is only a stand-in for the symbol; the device address comes
+// from hipGetSymbolAddress, once per device, and only that address is used.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr size_t CONS_FLAG_OFF = (size_t)MAX_RED_BLOCKS * 4 * sizeof(double);
+constexpr size_t CONS_OUT_OFF = CONS_FLAG_OFF + 256;
+static_assert(CONS_OUT_OFF + 4 * sizeof(double) <= STATIC_SCRATCH_BYTES, "scratch layout");
+
+constexpr int MAX_SCRATCH_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[MAX_SCRATCH_DEVICES] = {};
+
+// device address of `scratch` on `device` (looked up once per device, with
+// that device current; the caller's current device is restored)
+static hipError_t scratch_on(int device, unsigned char **out)
+{
+    if (device < 0 || device >= MAX_SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+// scratch bytes the reduction of this context needs (partials, counter, totals)
+size_t conserved_static_need(const lbm_ctx *c)
+{
+    const size_t part = (size_t)c->red_blocks * 4 * sizeof(double);
+    return (part <= CONS_FLAG_OFF ? CONS_FLAG_OFF : part) + 256 + 4 * sizeof(double);
+}
+
+hipError_t launch_conserved_static(lbm_ctx *c, double out[4], int *flag)
+{
+    if (conserved_static_need(c) > STATIC_SCRATCH_BYTES) return hipErrorInvalidValue;  // checked by the caller too
+    unsigned char *base = nullptr;
+    hipError_t e = scratch_on(c->device, &base);
+    if (e != hipSuccess) return e;
+    double *part = reinterpret_cast<double *>(base);
+    int *dflag = reinterpret_cast<int *>(base + CONS_FLAG_OFF);
+    double *dout = reinterpret_cast<double *>(base + CONS_OUT_OFF);
+    auto run = [&]() -> hipError_t { LBM_DISPATCH(conserved_st, c, part, dflag, dout) };
+    if ((e = run()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(out, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(flag, dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
+    return hipStreamSynchronize(c->stream);
+}
+
 hipError_t launch_copy(lbm_ctx *c, void *dst, const void *src, size_t bytes)
 {
     const int64_t n16 = (int64_t)(bytes / 16), tail = (int64_t)(bytes % 16);

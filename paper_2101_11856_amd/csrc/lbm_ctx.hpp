@@ -93,6 +93,12 @@ hipError_t launch_set_pop(lbm_ctx *c, const void *f);
 hipError_t launch_get_pop(lbm_ctx *c, void *f);
 hipError_t launch_macros(lbm_ctx *c, void *rho, void *u);
 hipError_t launch_conserved(lbm_ctx *c);
+// lbm_conserved_static: the same reduction with its partials, counter and
+// totals in the library's static scratch array of this GPU (no workspace use)
+constexpr int MAX_RED_BLOCKS = 1024;                    // per-block partials of the conservation totals
+constexpr size_t STATIC_SCRATCH_BYTES = 64 * 1024;      // static scratch array per GPU
+size_t conserved_static_need(const lbm_ctx *c);
+hipError_t launch_conserved_static(lbm_ctx *c, double out[4], int *flag);
 hipError_t launch_copy(lbm_ctx *c, void *dst, const void *src, size_t bytes);
 hipError_t launch_zero(lbm_ctx *c, void *dst, size_t bytes);
 hipError_t launch_scalar_io(lbm_ctx *c, float *dst, const float *src, bool to_state);

@@ -68,6 +68,7 @@ _SIG = {
     "lbm_step": [_vp, _i32],
     "lbm_macros": [_vp, _vp, _vp],
     "lbm_conserved": [_vp, C.POINTER(C.c_double)],
+    "lbm_conserved_static": [_vp, C.POINTER(C.c_double)],
     "lbm_ib_force": [_vp, C.POINTER(C.c_double)],
     "lbm_ib_force_eval": [_vp, C.POINTER(C.c_double)],
     "lbm_ib_torque": [_vp, C.POINTER(C.c_double)],
@@ -313,6 +314,13 @@ class Solver:
     def conserved(self) -> np.ndarray:
         out = (C.c_double * 4)()
         _check(_L.lbm_conserved(self._h, out), self._h)
+        return np.array(out[:])
+
+    def conserved_static(self) -> np.ndarray:
+        """conserved() through lbm_conserved_static (scratch in the library's
+        static device array; nothing allocated, calls on one GPU must not overlap)."""
+        out = (C.c_double * 4)()
+        _check(_L.lbm_conserved_static(self._h, out), self._h)
         return np.array(out[:])
 
     def ib_force(self) -> np.ndarray:
