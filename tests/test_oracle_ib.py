@@ -191,3 +191,29 @@ def test_penalty_force_uses_gain_and_area():
     G_hand = gain * rho0 * (ub - U[:, None])
     assert np.abs(G - G_hand).max() < 1e-15
     assert np.abs(F - G_hand @ area).max() < 1e-15
+
+
+def test_sample_order_hand_computed():
+    """Sec. 4.2.2 order worked out by hand on a 12x8x8 periodic grid (l = 4,
+    so 3 x 2 x 2 blocks, block index Bx + 3 (By + 2 Bz)); positions inside a
+    block are quantised to 256 steps per cell (1024 per block edge).
+      sample 0 (9.5, 1, 1)      block 2
+      sample 1 (1.25, 1, 1)     block 0, q = (320, 256, 256)
+      sample 2 (1, 1.25, 1)     block 0, q = (256, 320, 256)
+      sample 3 (5, 0.5, 0.5)    block 1
+      sample 4 (0.5, 4.5, 0.5)  block 3
+      sample 5 = sample 1       same key: the lower index first
+      sample 6 (0.5, 0.5, 4.5)  block 6
+      sample 7 (3.9, 3.9, 3.9)  block 0, q = (998, 998, 998): bit 9 set, last
+    Inside block 0, samples 1 and 2 first differ at bit 6 of q (320 = 256 +
+    64): x's bit lands at Morton position 18, y's at 19, so 1 < 2.  Sorted:
+    blocks 0 (1, 5, 2, 7), 1 (3), 2 (0), 3 (4), 6 (6)."""
+    xyz = np.array([[9.5, 1.25, 1.0, 5.0, 0.5, 1.25, 0.5, 3.9],
+                    [1.0, 1.0, 1.25, 0.5, 4.5, 1.0, 0.5, 3.9],
+                    [1.0, 1.0, 1.0, 0.5, 0.5, 1.0, 4.5, 3.9]], np.float32)
+    S = O.OracleSim(12, 8, 8, 0.1)
+    S.set_markers(xyz)
+    _, cell, perm = S.maps()
+    assert list(perm) == [1, 5, 2, 7, 3, 0, 4, 6]
+    # base cells x + 12 (y + 8 z) by hand
+    assert list(cell) == [9 + 12 * 9, 1 + 12 * 9, 1 + 12 * 9, 5, 48, 1 + 12 * 9, 384, 3 + 12 * (3 + 8 * 3)]
