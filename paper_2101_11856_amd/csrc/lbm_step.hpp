@@ -33,11 +33,19 @@ template <int ST> struct StepParams {
     const uint64_t *__restrict__ tile_mask;
     const int32_t *__restrict__ tile_start;
     const R4 *__restrict__ band_force;
+    // spreading finished inside the fused kernel (instead of k_spread): the
+    // run sums of the cells that target each band node, gathered in k_spread's order
+    int fused_spread;
+    int64_t nband, nruns;
+    const int32_t *__restrict__ band_src;
+    const uint8_t *__restrict__ run_cont;
+    const R4 *__restrict__ run_sum;
     const float *__restrict__ sc_in;
     float *__restrict__ sc_out;
     int sc_h;
     int load32;     // interior loads by 32-bit offsets from a per-wavefront base (blocked layout)
     uint32_t span;  // bytes from a row's lowest source row that cover its 9 source rows
+    float one;      // 1, as a run-time value (mixed-precision FP16 sums)
 };
 
 // ---------------------------------------------------------------------------
@@ -104,7 +112,57 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     const bool active = x < g.nx;
     const int xc = active ? x : g.nx - 1;
 
+    R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
+    if (BAND) {
+        const uint64_t mask = P.tile_mask[w];
+        if (mask != 0 && ((mask >> lane) & 1ull)) {
+            const int slot = P.tile_start[w] + __popcll(mask & ((1ull << lane) - 1ull));
+            if (P.fused_spread) {
+                R gx = 0, gy = 0, gz = 0;
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    int64_t src = P.band_src[(int64_t)d * P.nband + slot];
+                    if (src >= 0) {
+                        for (;;) {
+                            const auto v = P.run_sum[(int64_t)d * P.nruns + src];
+                            gx += v.x;
+                            gy += v.y;
+                            gz += v.z;
+                            if (src + 1 >= P.nruns || !P.run_cont[src + 1]) break;
+                            ++src;
+                        }
+                    }
+                }
+                Fx += gx;
+                Fy += gy;
+                Fz += gz;
+            } else {
+                const auto F = P.band_force[slot];
+                Fx += F.x;
+                Fy += F.y;
+                Fz += F.z;
+            }
+        }
+    }
     R f[3][3][3];
+    R rho, ux, uy, uz;
+    // FP16 deviations, central moments at unit high-order rates, interior
+    // rows: the halves go straight into the mixed-precision first stage
+    constexpr bool MIX = ST == LBM_F16DEV && COLL == COLL_CM_UNIT_HIGH && B32 && !ROW;
+    bool collided = false;
+    if constexpr (MIX) {
+        const bool yz = (y == 0 && g.face[2] != LBM_PERIODIC) || (y == g.ny - 1 && g.face[3] != LBM_PERIODIC) ||
+                        (z == 0 && g.face[4] != LBM_PERIODIC) || (z == g.nz - 1 && g.face[5] != LBM_PERIODIC);
+        const bool xf = (xs == 0 && g.face[0] != LBM_PERIODIC) || (xs == g.ntx - 1 && g.face[1] != LBM_PERIODIC);
+        const bool wrap = y == 0 || y == g.ny - 1 || z == 0 || z == g.nz - 1;
+        if (P.load32 && !yz && !xf && !wrap) {
+            _Float16 h[3][3][3];
+            pull_interior32_f16(h, P.fin, xc, y, z, g, P.span);
+            unit_high_from_low(low_moments_f16(h, P.one), f, Fx, Fy, Fz, P.rt, rho, ux, uy, uz);
+            collided = true;
+        }
+    }
+    if (!collided) {
     if constexpr (ROW) {
         __shared__ T row[Q][SEG * WAVES_PER_BLOCK];
         const bool yz = (y == 0 && g.face[2] != LBM_PERIODIC) || (y == g.ny - 1 && g.face[3] != LBM_PERIODIC) ||
@@ -151,20 +209,8 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     } else {
         pull_wave<ST>(f, P.fin, xs, xc, y, z, g, P.inlet);
     }
-
-    R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
-    if (BAND) {
-        const uint64_t mask = P.tile_mask[w];
-        if (mask != 0 && ((mask >> lane) & 1ull)) {
-            const int slot = P.tile_start[w] + __popcll(mask & ((1ull << lane) - 1ull));
-            const auto F = P.band_force[slot];
-            Fx += F.x;
-            Fy += F.y;
-            Fz += F.z;
-        }
-    }
-    R rho, ux, uy, uz;
     collide_as<COLL>(f, Fx, Fy, Fz, P.rt, rho, ux, uy, uz);
+    }
     if (active) {
         if constexpr (B32 && LBM_BUF_STORES) {
             const BufRsrc rout = make_rsrc(P.fout + row_off(g, y, z), (uint32_t)(Q * g.plane * (int64_t)sizeof(T)));
@@ -230,6 +276,8 @@ __global__ void __launch_bounds__(256)
 //     run(s) of the cell that targets it, in a fixed order.
 // No floating-point atomics anywhere: the step is bit-reproducible.
 // ---------------------------------------------------------------------------
+constexpr int64_t IB_SEG_MAX_BLOCKS = 4096;  // grid of k_ib_seg (FP64 partials summed by k_ib_total)
+
 template <typename R> struct IbParams {
     using R4 = typename R4T<R>::type;
     int64_t n, nruns, nband;
@@ -333,85 +381,89 @@ __global__ void __launch_bounds__(256) k_ib_seg(const IbParams<R> P)
 {
     using R4 = typename R4T<R>::type;
     const int64_t n = P.n;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;  // == k mod 64: runs restart at every window
-    const bool valid = k < n;
-    const int32_t c0 = valid ? P.slot[k] : -1;  // band slot of the base cell (offset 0) names the cell
-    const int32_t cprev = __shfl_up(c0, 1, 64);
-    const bool head = valid && (lane == 0 || c0 != cprev);
-    const uint64_t heads = __ballot(head);
-    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    const uint64_t hle = heads & upto;
-    const int first = hle ? 63 - __clzll(hle) : lane;   // first lane of this lane's run
-    const int dist = valid ? lane - first : 0;
-    const bool last = valid && (lane == 63 || k + 1 == n || ((heads >> (lane + 1)) & 1ull));
-
-    R v[8][3];
     double tot[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // force, then torque about (ox, oy, oz)
+    // grid-stride over 256-sample chunks (a bounded grid keeps the number of
+    // FP64 block partials small); every lane of a wave runs the same trips
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k - lane < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const bool valid = k < n;
+        const int32_t c0 = valid ? P.slot[k] : -1;  // band slot of the base cell (offset 0) names the cell
+        const int32_t cprev = __shfl_up(c0, 1, 64);
+        const bool head = valid && (lane == 0 || c0 != cprev);
+        const uint64_t heads = __ballot(head);
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const uint64_t hle = heads & upto;
+        const int first = hle ? 63 - __clzll(hle) : lane;  // first lane of this lane's run
+        const int dist = valid ? lane - first : 0;
+        const bool last = valid && (lane == 63 || k + 1 == n || ((heads >> (lane + 1)) & 1ull));
+
+        R v[8][3];
 #pragma unroll
-    for (int d = 0; d < 8; ++d) v[d][0] = v[d][1] = v[d][2] = (R)0;
-    if (valid) {
-        R t[3];
-        float p[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            p[a] = P.pos[a * n + k];
-            t[a] = (R)(p[a] - floorf(p[a]));
-        }
-        R K[8], rs = 0, us[3] = {0, 0, 0};
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const R4 node = P.band_ru[P.slot[(int64_t)d * n + k]];
-            K[d] = ((d & 1) ? t[0] : (R)1 - t[0]) * ((d & 2) ? t[1] : (R)1 - t[1]) * ((d & 4) ? t[2] : (R)1 - t[2]);
-            rs += K[d] * node.x;
-            us[0] += K[d] * node.y;
-            us[1] += K[d] * node.z;
-            us[2] += K[d] * node.w;
-        }
-        // Eq. (7) with the sample's gain; Eq. (8) carries the area weight
-        const R ag = (R)P.area[k] * (R)P.gain[k] * rs;
-        R aG[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            aG[a] = ag * ((R)P.ub[a * n + k] - us[a]);
-            tot[a] = (double)aG[a];
-        }
-        // Alg. 2 (c) torque: (x_s - o) x (a_s g_s), lever arm in FP64
-        const double rx = (double)p[0] - P.ox, ry = (double)p[1] - P.oy, rz = (double)p[2] - P.oz;
-        tot[3] = ry * (double)aG[2] - rz * (double)aG[1];
-        tot[4] = rz * (double)aG[0] - rx * (double)aG[2];
-        tot[5] = rx * (double)aG[1] - ry * (double)aG[0];
-#pragma unroll
-        for (int d = 0; d < 8; ++d)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) v[d][a] = K[d] * aG[a];
-    }
-    // segmented inclusive scan: after the steps with offsets 1, 2, 4, ... up
-    // to the longest run, the last lane of a run holds the run's sums (a
-    // fixed tree order, so repeated runs give the same bits)
-    int span = dist;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) span = max(span, __shfl_xor(span, off, 64));
-    span = __builtin_amdgcn_readfirstlane(span);
-    for (int off = 1; off <= span; off <<= 1) {
-#pragma unroll
-        for (int d = 0; d < 8; ++d)
+        for (int d = 0; d < 8; ++d) v[d][0] = v[d][1] = v[d][2] = (R)0;
+        if (valid) {
+            R t[3];
+            float p[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const R up = __shfl_up(v[d][a], off, 64);
-                if (dist >= off) v[d][a] += up;
+                p[a] = P.pos[a * n + k];
+                t[a] = (R)(p[a] - floorf(p[a]));
             }
-    }
-    if (last) {
-        const int64_t r = (int64_t)P.run_id[k - lane] + (int64_t)__popcll(hle) - 1;
+            R K[8], rs = 0, us[3] = {0, 0, 0};
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            R4 w;
-            w.x = v[d][0];
-            w.y = v[d][1];
-            w.z = v[d][2];
-            w.w = (R)0;
-            P.run_sum[(int64_t)d * P.nruns + r] = w;
+            for (int d = 0; d < 8; ++d) {
+                const R4 node = P.band_ru[P.slot[(int64_t)d * n + k]];
+                K[d] = ((d & 1) ? t[0] : (R)1 - t[0]) * ((d & 2) ? t[1] : (R)1 - t[1]) * ((d & 4) ? t[2] : (R)1 - t[2]);
+                rs += K[d] * node.x;
+                us[0] += K[d] * node.y;
+                us[1] += K[d] * node.z;
+                us[2] += K[d] * node.w;
+            }
+            // Eq. (7) with the sample's gain; Eq. (8) carries the area weight
+            const R ag = (R)P.area[k] * (R)P.gain[k] * rs;
+            R aG[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                aG[a] = ag * ((R)P.ub[a * n + k] - us[a]);
+                tot[a] += (double)aG[a];
+            }
+            // Alg. 2 (c) torque: (x_s - o) x (a_s g_s), lever arm in FP64
+            const double rx = (double)p[0] - P.ox, ry = (double)p[1] - P.oy, rz = (double)p[2] - P.oz;
+            tot[3] += ry * (double)aG[2] - rz * (double)aG[1];
+            tot[4] += rz * (double)aG[0] - rx * (double)aG[2];
+            tot[5] += rx * (double)aG[1] - ry * (double)aG[0];
+#pragma unroll
+            for (int d = 0; d < 8; ++d)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) v[d][a] = K[d] * aG[a];
+        }
+        // segmented inclusive scan: after the steps with offsets 1, 2, 4, ...
+        // up to the longest run, the last lane of a run holds the run's sums
+        // (a fixed tree order, so repeated runs give the same bits)
+        int span = dist;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) span = max(span, __shfl_xor(span, off, 64));
+        span = __builtin_amdgcn_readfirstlane(span);
+        for (int off = 1; off <= span; off <<= 1) {
+#pragma unroll
+            for (int d = 0; d < 8; ++d)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const R up = __shfl_up(v[d][a], off, 64);
+                    if (dist >= off) v[d][a] += up;
+                }
+        }
+        if (last) {
+            const int64_t r = (int64_t)P.run_id[k - lane] + (int64_t)__popcll(hle) - 1;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                R4 w;
+                w.x = v[d][0];
+                w.y = v[d][1];
+                w.z = v[d][2];
+                w.w = (R)0;
+                P.run_sum[(int64_t)d * P.nruns + r] = w;
+            }
         }
     }
     block_partial6(tot, P.part);
@@ -487,11 +539,18 @@ template <int ST> StepParams<ST> make_params(lbm_ctx *c)
     P.tile_mask = c->tile_mask;
     P.tile_start = c->tile_start;
     P.band_force = static_cast<const typename StepParams<ST>::R4 *>(c->band_force);
+    P.fused_spread = fused_spread(c) ? 1 : 0;
+    P.nband = c->nband;
+    P.nruns = c->nruns;
+    P.band_src = c->band_src;
+    P.run_cont = c->run_cont;
+    P.run_sum = static_cast<const typename StepParams<ST>::R4 *>(c->run_sum);
     P.sc_in = c->scA;
     P.sc_out = c->scB;
     P.sc_h = c->p.scalar_inlet_height;
     P.load32 = c->load32 ? 1 : 0;
     P.span = c->span32;
+    P.one = 1.0f;
     return P;
 }
 
@@ -522,7 +581,7 @@ template <int ST, int COLL> hipError_t fused_st(lbm_ctx *c)
     return hipGetLastError();
 }
 
-template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *ftot)
+template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *ftot, bool spread)
 {
     using R = typename Store<ST>::R;
     using R4 = typename StepParams<ST>::R4;
@@ -548,13 +607,15 @@ template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *f
     Q.ox = c->pose_o[0];
     Q.oy = c->pose_o[1];
     Q.oz = c->pose_o[2];
-    const int nblk = (int)(((c->ib_lane_per_run ? c->nruns : c->nm) + 255) / 256);
+    const int nblk = c->ib_lane_per_run ? (int)((c->nruns + 255) / 256)
+                                        : (int)std::min<int64_t>(IB_SEG_MAX_BLOCKS, (c->nm + 255) / 256);
     if (c->ib_lane_per_run) hipLaunchKernelGGL((k_ib_run<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
     else hipLaunchKernelGGL((k_ib_seg<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
     hipLaunchKernelGGL(k_ib_total<>, dim3(1), dim3(256), 0, c->stream, c->ib_part, nblk, ftot);
-    hipLaunchKernelGGL((k_spread<R>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, c->nband, c->nruns,
-                       c->band_src, c->run_cont, static_cast<const R4 *>(c->run_sum),
-                       static_cast<R4 *>(c->band_force));
+    if (spread)
+        hipLaunchKernelGGL((k_spread<R>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, c->nband, c->nruns,
+                           c->band_src, c->run_cont, static_cast<const R4 *>(c->run_sum),
+                           static_cast<R4 *>(c->band_force));
     return hipGetLastError();
 }
 

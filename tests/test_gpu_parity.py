@@ -142,12 +142,15 @@ def _ib_scene(nx, ny, nz, seed):
     sph = synth.fibonacci_sphere(400, 5.0, (12.3, ny / 2 + 0.2, nz / 2 - 0.1))
     box = synth.random_box(2000, (26.0, 6.0, 5.0), (32.0, 12.0, 11.0), seed + 1)  # many samples per cell
     on_nodes = np.array([[20.0, 21.0, 30.5], [4.0, 5.0, 6.0], [3.0, 3.0, 8.0]], np.float32)
-    xyz = np.concatenate([sph, box, on_nodes], axis=1)
+    # next to the y faces: band nodes on the low face (a no-slip wall in the
+    # wall case) and on the high face (free slip there)
+    at_faces = np.array([[35.5, 36.25], [0.5, ny - 1.75], [8.5, 3.5]], np.float32)
+    xyz = np.concatenate([sph, box, on_nodes, at_faces], axis=1)
     n = xyz.shape[1]
     ub = (0.01 * rng.standard_normal((3, n))).astype(np.float32)
     # area per sample ~ surface (or volume) per sample, so that the summed
     # a_s gamma_s per cell stays O(1) (explicit penalty forcing)
-    area = np.concatenate([np.full(400, 4 * np.pi * 25.0 / 400), np.full(2000, 216.0 / 2000), np.ones(3)])
+    area = np.concatenate([np.full(400, 4 * np.pi * 25.0 / 400), np.full(2000, 216.0 / 2000), np.ones(3), np.ones(2)])
     area = (area * (0.7 + 0.6 * rng.random(n))).astype(np.float32)
     gain = (0.5 + rng.random(n)).astype(np.float32)
     return xyz, ub, area, gain
