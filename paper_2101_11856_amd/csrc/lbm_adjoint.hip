@@ -3,6 +3,8 @@
 // For lambda = dJ/df(n+1) and the forward state f(n) (read from a tape), one
 // adjoint step computes dJ/df(n) and accumulates parameter gradients:
 //   k_adj_collide  per node: recompute the pull and the force, collision VJP
+//                  (the general central-moment form, or the form for unit
+//                  rates of orders 3 to 6 that the forward step then uses)
 //                  -> mu = dJ/df*(x), phi = dJ/dF(x) at band nodes
 //   k_adj_ib       per sample: spreading transposed = gather of phi;
 //                  penalty (Eq. 7) reversed -> dJ/dgamma_s; interpolation
@@ -57,7 +59,8 @@ __device__ __forceinline__ void node_of_item(const Geom &g, int64_t w, int lane,
 // FP32 arithmetic forms: capped at 128 VGPRs (4 waves per SIMD instead of 3). The band variant
 // then spills 2 VGPRs, the band-free one 26; the backward step still runs 4% faster. The FP64
 // form would spill about 300 and keeps the compiler's choice.
-template <int ST, bool BAND>
+// UNIT: the orders 3 to 6 relax at rate 1 (the forward step's collide_unit_high).
+template <int ST, bool BAND, bool UNIT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == LBM_F64 ? 1 : 4)))
 k_adj_collide(const AdjParams<ST> P)
 {
@@ -89,7 +92,8 @@ k_adj_collide(const AdjParams<ST> P)
 #pragma unroll
     for (int i = 0; i < Q; ++i) lam[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = P.lam[(int64_t)i * g.plane + base];
     R Fb[3] = {0, 0, 0};
-    collide_vjp(f, Fx, Fy, Fz, P.rt, lam, Fb[0], Fb[1], Fb[2]);
+    if constexpr (UNIT) collide_unit_high_vjp(f, Fx, Fy, Fz, P.rt, lam, Fb[0], Fb[1], Fb[2]);
+    else collide_vjp(f, Fx, Fy, Fz, P.rt, lam, Fb[0], Fb[1], Fb[2]);
     if (!active) return;
 #pragma unroll
     for (int i = 0; i < Q; ++i) P.M[(int64_t)i * g.plane + base] = lam[CZ[i] + 1][CY[i] + 1][CX[i] + 1];
@@ -423,8 +427,13 @@ template <int ST> static hipError_t step_st(lbm_ctx *c, const void *state, doubl
     if (c->nm > 0 && (e = launch_band_ib(c, state, c->ftot_eval)) != hipSuccess) return e;
     const AdjParams<ST> P = adj_params<ST>(c, state);
     const dim3 grid((unsigned)((c->g.W + 3) / 4)), block(256);
-    if (c->nm > 0) hipLaunchKernelGGL((k_adj_collide<ST, true>), grid, block, 0, c->stream, P);
-    else hipLaunchKernelGGL((k_adj_collide<ST, false>), grid, block, 0, c->stream, P);
+    if (c->coll == COLL_CM_UNIT_HIGH) {
+        if (c->nm > 0) hipLaunchKernelGGL((k_adj_collide<ST, true, true>), grid, block, 0, c->stream, P);
+        else hipLaunchKernelGGL((k_adj_collide<ST, false, true>), grid, block, 0, c->stream, P);
+    } else {
+        if (c->nm > 0) hipLaunchKernelGGL((k_adj_collide<ST, true, false>), grid, block, 0, c->stream, P);
+        else hipLaunchKernelGGL((k_adj_collide<ST, false, false>), grid, block, 0, c->stream, P);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (c->nm > 0 && (e = adj_ib_part<R>(c, g_gain)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_adj_gather<R>), grid, block, 0, c->stream, c->g, static_cast<const R *>(c->adjM),

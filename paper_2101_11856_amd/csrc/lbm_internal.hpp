@@ -811,9 +811,11 @@ __device__ __forceinline__ Low<float> low_moments_f16(const _Float16 (&h)[3][3][
 // moments relax fully, kappa' = kappa_eq + kappa_F / 2, so they depend on
 // rho, u and F only and the forward transform is needed up to order 2.  Same
 // post-collision state as collide() up to rounding.
+// The post-collision central moments kappa' of collide_unit_high (into k),
+// from the raw moments of orders 0-2; also rho and the half-force velocity.
 template <typename R>
-__host__ __device__ __forceinline__ void unit_high_from_low(const Low<R> &L, R (&f)[3][3][3], R Fx, R Fy, R Fz,
-                                                            const Rates<R> &rt, R &rho_o, R &ux_o, R &uy_o, R &uz_o)
+__host__ __device__ __forceinline__ void unit_high_kappa(const Low<R> &L, R (&f)[3][3][3], R Fx, R Fy, R Fz,
+                                                         const Rates<R> &rt, R &rho_o, R &ux_o, R &uy_o, R &uz_o)
 {
     const R drho = L.m000;
     const R inv = (R)1 / ((R)1 + drho);
@@ -871,7 +873,13 @@ __host__ __device__ __forceinline__ void unit_high_from_low(const Low<R> &L, R (
     f[2][1][2] = uy * px * pz + f5 * Fy;               // (2,1,2)
     f[1][2][2] = uz * px * py + f5 * Fz;               // (2,2,1)
     f[2][2][2] = drho * t27 - ((x2 * y2 + x2 * z2 + y2 * z2) * third + (x2 + y2 + z2) * ninth + x2 * y2 * z2);
-    central_to_populations(f, ux, uy, uz);
+}
+template <typename R>
+__host__ __device__ __forceinline__ void unit_high_from_low(const Low<R> &L, R (&f)[3][3][3], R Fx, R Fy, R Fz,
+                                                            const Rates<R> &rt, R &rho_o, R &ux_o, R &uy_o, R &uz_o)
+{
+    unit_high_kappa(L, f, Fx, Fy, Fz, rt, rho_o, ux_o, uy_o, uz_o);
+    central_to_populations(f, ux_o, uy_o, uz_o);
 }
 template <typename R>
 __host__ __device__ __forceinline__ void collide_unit_high(R (&f)[3][3][3], R Fx, R Fy, R Fz, const Rates<R> &rt,

@@ -228,6 +228,15 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
         }
     }
     if (SCALAR) scalar_update<ST>(P, xc, y, z, (float)ux, (float)uy, (float)uz, active);
+    // lanes in the row's x padding (nx <= x < nxp, last segment only) store
+    // zeros, so that every byte of a state this kernel writes is defined (a
+    // state written straight into a tape slot equals a copy of the same state)
+    if (xs == g.ntx - 1 && !active && x < g.nxp) {
+        const int64_t base = row_off(g, y, z) + x;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) P.fout[(int64_t)i * g.plane + base] = (T)0;
+        if (SCALAR) P.sc_out[((int64_t)z * g.ny + y) * g.nxp + x] = 0.f;
+    }
 }
 
 // ---------------------------------------------------------------------------
