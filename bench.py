@@ -300,8 +300,8 @@ def moving_torus_workload(steps, warmup):
     scene size): torus major radius 48, minor 16, 273k samples, tilted 0.5 rad
     about x and turning about its own axis at rim speed 0.05.  Every step
     places the samples at the new pose (rigid update, re-sort, re-band) and
-    then advances; timed by the host clock around whole steps, since placing
-    the samples waits for its own counts.  The same scene held still gives the
+    then advances; timed by the host clock around whole steps (a device
+    synchronisation on both sides).  The same scene held still gives the
     share of the re-placement."""
     import numpy as np
     import torch

@@ -186,7 +186,18 @@ lbm_status lbm_set_solids(lbm_ctx *ctx, int64_t n, const float *xyz, const float
  * the domain (same rule as lbm_set_solids) the call returns LBM_E_INVAL and
  * the previous pose stays in force.  Call it before each lbm_step(1) to move
  * the solid every step.  Any adjoint workspace must be bound again
- * (lbm_adjoint_init) afterwards.  Sync. */
+ * (lbm_adjoint_init) afterwards.
+ * Waiting: the first call after lbm_set_solids / lbm_set_body takes the
+ * body-frame bounding box of the samples (Sync).  A pose for which that box
+ * shows on the host that every sample stays inside (interval bounds with a
+ * margin far above the placement's rounding) is placed without waiting
+ * (Async): the new band and run counts stay on the device, where the kernels
+ * of lbm_step read them.  Any other pose first has the device count the
+ * samples outside the domain (Sync), which decides the LBM_E_INVAL above.
+ * Should a pose placed without waiting still put a sample outside, that
+ * sample is clamped into the domain and the next lbm_ib_force,
+ * lbm_ib_torque, lbm_ib_force_eval, lbm_conserved or adjoint call returns
+ * LBM_E_INVAL. */
 lbm_status lbm_set_pose(lbm_ctx *ctx, const double R[9], const double o[3], const double v[3], const double w[3]);
 
 /* lbm_set_solids for a moving solid: X (device float[3][n]) are body

@@ -387,6 +387,8 @@ static lbm_status set_samples(lbm_ctx *c, const char *who, int64_t n, const floa
         return fail(c, LBM_E_NOMEM, "marker workspace too small: need " + std::to_string(L.total) + " bytes");
     c->nm = 0;
     c->nband = 0;
+    c->counts_exact = true;
+    c->pose_pending = false;
     c->mws = static_cast<char *>(marker_ws);
     c->mws_bytes = marker_ws_bytes;
     int bad = 0;
@@ -394,10 +396,10 @@ static lbm_status set_samples(lbm_ctx *c, const char *who, int64_t n, const floa
     if (e == hipSuccess) {
         if (R) {
             c->nm = n;  // solids_pose places the c->nm body samples
-            e = solids_pose(c, R, o, v, w, &bad);
+            e = solids_pose(c, R, o, v, w, true, &bad);
             if (e != hipSuccess || bad) c->nm = 0;
         } else {
-            e = solids_setup(c, n, c->b_xyz, c->b_ub, c->b_area, c->b_gain, &bad);
+            e = solids_setup(c, n, c->b_xyz, c->b_ub, c->b_area, c->b_gain, false, true, &bad);
         }
     }
     if (e != hipSuccess) return hip_fail(c, e, who);
@@ -429,15 +431,67 @@ lbm_status lbm_set_body(lbm_ctx *c, int64_t n, const float *X, const float *ub, 
     return set_samples(c, "lbm_set_body", n, X, ub, area, gain, marker_ws, marker_ws_bytes, R, o, v, w);
 }
 
+// Whether every sample placed at (R, o) is inside the domain, shown from the
+// body-frame bounding box: interval bounds of o_a + sum_b R_ab X_b over the
+// box, widened by a margin far above the rounding of the FP64 placement and
+// of its FP32 result.  False when that cannot be shown (the device then
+// counts the samples outside).
+static bool pose_inside(const lbm_ctx *c, const double R[9], const double o[3])
+{
+    if (c->box_state != 1) return false;
+    const int n[3] = {c->g.nx, c->g.ny, c->g.nz};
+    for (int a = 0; a < 3; ++a) {
+        double lo = o[a], hi = o[a], mag = std::fabs(o[a]);
+        for (int b = 0; b < 3; ++b) {
+            const double p = R[3 * a + b] * c->box_lo[b], q = R[3 * a + b] * c->box_hi[b];
+            lo += std::min(p, q);
+            hi += std::max(p, q);
+            mag += std::max(std::fabs(p), std::fabs(q));
+        }
+        const double margin = (mag + 1.0) * 0x1p-20;
+        const double top = c->g.face[2 * a] == LBM_PERIODIC ? n[a] : n[a] - 1;
+        if (!(lo - margin >= 0.0) || !(hi + margin < top)) return false;
+    }
+    return true;
+}
+
+// Reads the device counts of a set-up that did not wait for them and, for a
+// pose placed without waiting, its count of samples outside the domain
+// (which the host bound makes zero; a nonzero count is reported here).
+static lbm_status settle_counts(lbm_ctx *c, const char *who)
+{
+    if (c->nm == 0 || (c->counts_exact && !c->pose_pending)) return LBM_OK;
+    int bad = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bad, c->dbad, sizeof(int), hipMemcpyDeviceToHost, c->stream), who);
+    HIP_TRY(c, read_counts(c), who);
+    const bool pending = c->pose_pending;
+    c->pose_pending = false;
+    if (pending && bad) {
+        HIP_TRY(c, launch_zero(c, c->dbad, sizeof(int)), who);
+        return fail(c, LBM_E_INVAL,
+                    std::to_string(bad) + " sample(s) of an earlier pose were placed outside the domain and clamped");
+    }
+    return LBM_OK;
+}
+
 lbm_status lbm_set_pose(lbm_ctx *c, const double R[9], const double o[3], const double v[3], const double w[3])
 {
     CHECK_CTX(c);
     if (!R || !o || !v || !w) return fail(c, LBM_E_INVAL, "R, o, v and w must be non-NULL");
     if (!finite_pose(R, o, v, w)) return fail(c, LBM_E_INVAL, "R, o, v and w must be finite");
     if (c->nm == 0) return fail(c, LBM_E_STATE, "no solid samples (lbm_set_solids)");
+    if (c->box_state == 0) HIP_TRY(c, body_box(c), "lbm_set_pose");
+    // Shown inside on the host: no wait (the set-up runs behind the caller's
+    // queue).  Otherwise the device counts the samples outside first.
+    const bool inside = pose_inside(c, R, o);
+    if (!inside) {
+        const lbm_status st = settle_counts(c, "lbm_set_pose");
+        if (st != LBM_OK) return st;
+    }
     int bad = 0;
-    const hipError_t e = solids_pose(c, R, o, v, w, &bad);
+    const hipError_t e = solids_pose(c, R, o, v, w, !inside, &bad);
     if (e != hipSuccess) return hip_fail(c, e, "lbm_set_pose");
+    if (inside) c->pose_pending = true;
     if (bad) {
         return fail(c, LBM_E_INVAL,
                     std::to_string(bad) +
@@ -482,6 +536,8 @@ lbm_status lbm_conserved(lbm_ctx *c, double out[4])
 {
     CHECK_CTX(c);
     if (!out) return fail(c, LBM_E_INVAL, "out is NULL");
+    const lbm_status st = settle_counts(c, "lbm_conserved");
+    if (st != LBM_OK) return st;
     HIP_TRY(c, launch_conserved(c), "lbm_conserved");
     int flag = 0;
     HIP_TRY(c, hipMemcpyAsync(out, c->red_out, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "lbm_conserved");
@@ -510,6 +566,8 @@ lbm_status lbm_ib_force(lbm_ctx *c, double out[3])
 {
     CHECK_CTX(c);
     if (!out) return fail(c, LBM_E_INVAL, "out is NULL");
+    const lbm_status st = settle_counts(c, "lbm_ib_force");
+    if (st != LBM_OK) return st;
     HIP_TRY(c, hipMemcpyAsync(out, c->ftot, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "lbm_ib_force");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "lbm_ib_force");
     return LBM_OK;
@@ -519,6 +577,8 @@ lbm_status lbm_ib_torque(lbm_ctx *c, double out[3])
 {
     CHECK_CTX(c);
     if (!out) return fail(c, LBM_E_INVAL, "out is NULL");
+    const lbm_status st = settle_counts(c, "lbm_ib_torque");
+    if (st != LBM_OK) return st;
     HIP_TRY(c, hipMemcpyAsync(out, c->ftot + 3, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "lbm_ib_torque");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "lbm_ib_torque");
     return LBM_OK;
@@ -532,6 +592,8 @@ lbm_status lbm_ib_force_eval(lbm_ctx *c, double out[3])
         out[0] = out[1] = out[2] = 0.0;
         return LBM_OK;
     }
+    const lbm_status st = settle_counts(c, "lbm_ib_force_eval");
+    if (st != LBM_OK) return st;
     HIP_TRY(c, launch_band_ib(c, c->fA, c->ftot_eval), "lbm_ib_force_eval");
     HIP_TRY(c, hipMemcpyAsync(out, c->ftot_eval, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
             "lbm_ib_force_eval");
@@ -631,6 +693,9 @@ lbm_status lbm_record_tape(lbm_ctx *c, int32_t nsteps, void *tape)
 lbm_status lbm_adjoint_ws_size(const lbm_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return fail(const_cast<lbm_ctx *>(c), LBM_E_INVAL, "NULL argument");
+    // the size depends on the band count, which may still be on the device
+    const lbm_status st = settle_counts(const_cast<lbm_ctx *>(c), "lbm_adjoint_ws_size");
+    if (st != LBM_OK) return st;
     *bytes = adjoint_ws_bytes(c);
     return LBM_OK;
 }
@@ -642,6 +707,8 @@ lbm_status lbm_adjoint_init(lbm_ctx *c, void *adj_ws, size_t bytes)
         return fail(c, LBM_E_UNSUPPORTED, "the adjoint differentiates the central-moment collision only");
     if (!adj_ws || reinterpret_cast<uintptr_t>(adj_ws) % ALIGN)
         return fail(c, LBM_E_INVAL, "adjoint workspace must be non-NULL and 256-byte aligned");
+    const lbm_status st = settle_counts(c, "lbm_adjoint_init");
+    if (st != LBM_OK) return st;
     if (bytes < adjoint_ws_bytes(c))
         return fail(c, LBM_E_NOMEM, "adjoint workspace too small: need " + std::to_string(adjoint_ws_bytes(c)) + " bytes");
     adjoint_bind(c, adj_ws, bytes);
@@ -652,6 +719,8 @@ lbm_status lbm_adjoint_init(lbm_ctx *c, void *adj_ws, size_t bytes)
 static lbm_status adjoint_ready(lbm_ctx *c)
 {
     if (!c->aws) return fail(c, LBM_E_STATE, "lbm_adjoint_init has not been called");
+    const lbm_status st = settle_counts(c, "adjoint");
+    if (st != LBM_OK) return st;
     if (c->nm > 0 && c->nband > c->adj_band_cap)
         return fail(c, LBM_E_STATE, "samples changed after lbm_adjoint_init; call it again");
     return LBM_OK;

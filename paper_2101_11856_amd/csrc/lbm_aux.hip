@@ -197,30 +197,74 @@ __global__ void k_scalar_io(Geom g, float *__restrict__ dst, const float *__rest
 }
 
 // ---------------------------------------------------------------------------
-// solid samples (Sec. 4.2.2): keys, sort, band tiles, slots
+// solid samples (Sec. 4.2.2): keys, sort, band tiles, slots, runs
+//
+// The sort orders the samples by (l^3 block in x-y-z order, Morton order of
+// the quantised position inside the block, input index).  It runs as a
+// bucket sort with one bucket per block: a histogram of the blocks (integer
+// atomics), an exclusive scan of it, a scatter of the samples into their
+// bucket's range (in any order), then every bucket ordered on its own by the
+// unique key (Morton code, index).  Buckets of at most RANK_MAX samples take
+// counting ranks, one lane per sample; larger ones a bitonic network run by
+// one workgroup.  The result does not depend on the scatter's order.
 // ---------------------------------------------------------------------------
 constexpr int ELL = 4;
+constexpr int RANK_MAX = 2048;
+constexpr int BIG_SORT_BLOCKS = 64;
 
 struct MarkerGeom {
     int nx, ny, nz, nbx, nby, ntx;
     int periodic[3];
 };
 
-// Checks, base cell and sort key of each sample (input order).
+__device__ __forceinline__ float domain_top(const MarkerGeom &mg, int a)
+{
+    const int n = a == 0 ? mg.nx : a == 1 ? mg.ny : mg.nz;
+    return mg.periodic[a] ? (float)n : (float)(n - 1);
+}
+
+// Integer atomic add of `delta` per lane to p[key], one atomic per distinct
+// key of the wavefront's active lanes (their leader adds the group's total):
+// samples in input order tend to share blocks, and same-address atomics
+// serialise.  Returns the value before the group's add, minus `delta` times
+// the number of lower lanes in the group, i.e. a slot of the lane's own.
+__device__ __forceinline__ int32_t wave_grouped_add(int32_t *p, int32_t key, int32_t delta)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t todo = __ballot(1);
+    int32_t mine = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int32_t kl = __shfl(key, leader, 64);
+        const uint64_t same = __ballot(key == kl);
+        int32_t old = 0;
+        if (lane == leader) old = atomicAdd(p + kl, delta * (int32_t)__popcll(same));
+        old = __shfl(old, leader, 64);
+        if (key == kl) mine = old + delta * (int32_t)__popcll(same & below);
+        todo &= ~same;
+    }
+    return mine;
+}
+
+// Checks, base cell and sort key of each sample (input order), and the
+// histogram of the blocks.  Also clears the base-cell bit map and the count
+// of large buckets, which later launches fill.
 __global__ void k_mk_keys(MarkerGeom mg, int64_t n, const float *__restrict__ xyz, unsigned long long *__restrict__ keys,
-                          int32_t *__restrict__ idx, int32_t *__restrict__ cell, int *__restrict__ bad)
+                          int32_t *__restrict__ cell, int32_t *__restrict__ bcount, int *__restrict__ bad,
+                          unsigned long long *__restrict__ occ, int64_t W, int32_t *__restrict__ nbig)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t w = s; w < W; w += (int64_t)gridDim.x * blockDim.x) occ[w] = 0ull;
+    if (s == 0) *nbig = 0;
     if (s >= n) return;
-    const int nn[3] = {mg.nx, mg.ny, mg.nz};
     int b[3], B[3];
     unsigned q[3];
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float p = xyz[a * n + s];
-        const float hi = mg.periodic[a] ? (float)nn[a] : (float)(nn[a] - 1);
-        if (!(p >= 0.0f) || !(p < hi)) ok = false;
+        if (!(p >= 0.0f) || !(p < domain_top(mg, a))) ok = false;
         b[a] = ok ? (int)floorf(p) : 0;
         B[a] = b[a] / ELL;
         // (x - l B) * (1024 / l): exact in FP32
@@ -228,7 +272,6 @@ __global__ void k_mk_keys(MarkerGeom mg, int64_t n, const float *__restrict__ xy
         r = fminf(fmaxf(r, 0.0f), 1023.0f);
         q[a] = ok ? (unsigned)r : 0u;
     }
-    if (!ok) atomicAdd(bad, 1);
     unsigned long long morton = 0;
 #pragma unroll
     for (int bit = 0; bit < 10; ++bit)
@@ -236,15 +279,100 @@ __global__ void k_mk_keys(MarkerGeom mg, int64_t n, const float *__restrict__ xy
         for (int a = 0; a < 3; ++a) morton |= (unsigned long long)((q[a] >> bit) & 1u) << (3 * bit + a);
     const unsigned long long block =
         (unsigned long long)B[0] + (unsigned long long)mg.nbx * ((unsigned long long)B[1] + (unsigned long long)mg.nby * B[2]);
+    // a sample outside the domain stops the set-up before the scatter; the
+    // caller then clears the histogram again
+    if (ok) wave_grouped_add(bcount, (int32_t)block, 1);
+    else atomicAdd(bad, 1);
     keys[s] = (block << 30) | morton;
-    idx[s] = (int32_t)s;
     cell[s] = (int32_t)((int64_t)b[0] + (int64_t)mg.nx * ((int64_t)b[1] + (int64_t)mg.ny * b[2]));
 }
 
-__global__ void k_mk_gather(int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ xyz,
-                            const float *__restrict__ ub, const float *__restrict__ area, const float *__restrict__ gain,
-                            float *__restrict__ pos_s, float *__restrict__ ub_s, float *__restrict__ area_s,
-                            float *__restrict__ gain_s)
+// Each sample into its block's range, at the position its atomic decrement of
+// the block's count returns (so the counts are zero again afterwards); the
+// bucket-local key is (Morton code, input index).
+__global__ void k_scatter(int64_t n, const unsigned long long *__restrict__ keys, const int32_t *__restrict__ bstart,
+                          int32_t *__restrict__ bcount, uint32_t *__restrict__ tb, unsigned long long *__restrict__ tkk)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const unsigned long long key = keys[s];
+    const uint32_t b = (uint32_t)(key >> 30);
+    const int32_t p = bstart[b] + wave_grouped_add(bcount, (int32_t)b, -1) - 1;
+    tb[p] = b;
+    tkk[p] = ((key & ((1ull << 30) - 1ull)) << 31) | (unsigned long long)s;
+}
+
+// Counting ranks inside a bucket: the sample of rank r (number of smaller
+// keys; the keys are unique) goes to the bucket's position r.  Buckets above
+// RANK_MAX are listed for k_bucket_big.
+__global__ void k_bucket_rank(int64_t n, const int32_t *__restrict__ bstart, const uint32_t *__restrict__ tb,
+                              const unsigned long long *__restrict__ tkk, int32_t *__restrict__ perm,
+                              int32_t *__restrict__ big, int32_t *__restrict__ nbig)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t b = tb[k];
+    const int32_t lo = bstart[b], hi = bstart[b + 1];
+    if (hi - lo > RANK_MAX) {
+        if (k == lo) big[atomicAdd(nbig, 1)] = (int32_t)b;
+        return;
+    }
+    const unsigned long long kk = tkk[k];
+    int32_t r = 0, j = lo;
+    for (; j + 8 <= hi; j += 8) {  // eight loads in flight
+        unsigned long long v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = tkk[j + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) r += v[u] < kk ? 1 : 0;
+    }
+    for (; j < hi; ++j) r += tkk[j] < kk ? 1 : 0;
+    perm[lo + r] = (int32_t)(kk & 0x7fffffffull);
+}
+
+// Buckets above RANK_MAX: a bitonic network over the bucket in place (every
+// comparator ascending, the first of each merge against the mirrored
+// partner, so that the virtual +inf padding up to a power of two never
+// moves), one workgroup per listed bucket.  Exits at once when none is
+// listed.
+__global__ void __launch_bounds__(1024) k_bucket_big(const int32_t *__restrict__ bstart, const int32_t *__restrict__ big,
+                                                     const int32_t *__restrict__ nbig,
+                                                     unsigned long long *__restrict__ tkk, int32_t *__restrict__ perm)
+{
+    const int32_t m = *nbig;
+    for (int32_t e = blockIdx.x; e < m; e += gridDim.x) {
+        const uint32_t b = (uint32_t)big[e];
+        const int32_t lo = bstart[b], c = bstart[b + 1] - lo;
+        unsigned long long *a = tkk + lo;
+        int32_t P = 1;
+        while (P < c) P <<= 1;
+        for (int32_t k = 2; k <= P; k <<= 1)
+            for (int32_t j = k >> 1; j > 0; j >>= 1) {
+                for (int32_t i = threadIdx.x; i < c; i += blockDim.x) {
+                    const int32_t l = j == (k >> 1) ? (i ^ (k - 1)) : (i ^ j);
+                    if (l > i && l < c) {
+                        const unsigned long long u = a[i], v = a[l];
+                        if (u > v) {
+                            a[i] = v;
+                            a[l] = u;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int32_t i = threadIdx.x; i < c; i += blockDim.x) perm[lo + i] = (int32_t)(a[i] & 0x7fffffffull);
+        __syncthreads();
+    }
+}
+
+// Sorted copies of the sample data; run heads (a new base cell, or every
+// 64th sorted sample: the window of one spreading wavefront); the bit of each
+// base cell in the base-cell map (set by the first sample of the cell).
+__global__ void k_mk_gather(MarkerGeom mg, int64_t n, const int32_t *__restrict__ perm, const int32_t *__restrict__ cell,
+                            const float *__restrict__ xyz, const float *__restrict__ ub, const float *__restrict__ area,
+                            const float *__restrict__ gain, float *__restrict__ pos_s, float *__restrict__ ub_s,
+                            float *__restrict__ area_s, float *__restrict__ gain_s, int32_t *__restrict__ head,
+                            unsigned long long *__restrict__ occ)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -256,6 +384,149 @@ __global__ void k_mk_gather(int64_t n, const int32_t *__restrict__ perm, const f
     }
     area_s[k] = area ? area[s] : 1.0f;
     gain_s[k] = gain ? gain[s] : 1.0f;
+    const int32_t ck = cell[s];
+    const bool first = k == 0 || cell[perm[k - 1]] != ck;
+    head[k] = (first || (k & 63) == 0) ? 1 : 0;
+    if (first) {
+        const int x = ck % mg.nx;
+        const int64_t row = ck / mg.nx;
+        atomicOr(occ + row * mg.ntx + x / SEG, 1ull << (x % SEG));
+    }
+}
+
+// Band tiles: node (x, y, z) receives force when one of the base cells
+// (x, y, z) - d, d in {0, 1}^3, holds a sample (the 2x2x2 stencil, wrapped on
+// periodic axes), i.e. the base-cell map dilated by one node towards +x, +y,
+// +z.  One lane per 64-node word; also the word's node count.
+__global__ void k_dilate(MarkerGeom mg, int64_t W, const unsigned long long *__restrict__ occ,
+                         unsigned long long *__restrict__ mask, int32_t *__restrict__ cnt)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= W) return;
+    const int xs = (int)(w % mg.ntx);
+    const int64_t row = w / mg.ntx;
+    const int y = (int)(row % mg.ny), z = (int)(row / mg.ny);
+    unsigned long long m = 0;
+    for (int dz = 0; dz < 2; ++dz) {
+        int zz = z - dz;
+        if (zz < 0) {
+            if (!mg.periodic[2]) continue;
+            zz += mg.nz;
+        }
+        for (int dy = 0; dy < 2; ++dy) {
+            int yy = y - dy;
+            if (yy < 0) {
+                if (!mg.periodic[1]) continue;
+                yy += mg.ny;
+            }
+            const int64_t rb = ((int64_t)zz * mg.ny + yy) * mg.ntx;
+            const unsigned long long o = occ[rb + xs];
+            m |= o | (o << 1);
+            if (xs > 0) {
+                m |= occ[rb + xs - 1] >> 63;
+            } else if (mg.periodic[0]) {
+                const int xl = mg.nx - 1;
+                m |= (occ[rb + xl / SEG] >> (xl % SEG)) & 1ull;
+            }
+        }
+    }
+    // the shift of a base cell at x = nx - 1 (periodic x) lands past the row
+    // end; its node x = 0 was taken above
+    const int valid = mg.nx - xs * SEG;
+    if (valid < SEG) m &= (1ull << valid) - 1ull;
+    mask[w] = m;
+    cnt[w] = __popcll(m);
+}
+
+// Band list (node index of each band slot, in node order), with the 8 run
+// entries of each band node cleared; the tile starts corrected for the run
+// heads that precede the tile counts in the shared scan; the last lane also
+// stores the band and run counts.
+__global__ void k_band_list(MarkerGeom mg, int64_t W, const unsigned long long *__restrict__ mask,
+                            int32_t *__restrict__ start, int32_t *__restrict__ band_cell,
+                            int32_t *__restrict__ band_src, int64_t bstride, int64_t n,
+                            const int32_t *__restrict__ rid, const int32_t *__restrict__ head,
+                            int32_t *__restrict__ counts)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= W) return;
+    unsigned long long m = mask[w];
+    const int32_t nruns = rid[n - 1] + head[n - 1];
+    const int32_t s0 = start[w] - nruns;  // the scan ran over the run heads first
+    start[w] = s0;
+    if (w == W - 1) {
+        counts[0] = s0 + __popcll(m);
+        counts[1] = nruns;
+    }
+    if (!m) return;
+    const int xs = (int)(w % mg.ntx);
+    const int64_t row = w / mg.ntx;
+    int r = s0;
+    while (m) {
+        const int bit = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        band_cell[r] = (int32_t)(row * mg.nx + xs * SEG + bit);
+#pragma unroll
+        for (int d = 0; d < 8; ++d) band_src[(int64_t)d * bstride + r] = -1;
+        ++r;
+    }
+}
+
+__device__ __forceinline__ void stencil_node(const MarkerGeom &mg, const float *pos, int64_t n, int64_t k, int d, int &x,
+                                             int &y, int &z)
+{
+    const int nn[3] = {mg.nx, mg.ny, mg.nz};
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int v = (int)floorf(pos[a * n + k]) + ((d >> a) & 1);
+        if (v >= nn[a]) v -= nn[a];
+        c[a] = v;
+    }
+    x = c[0];
+    y = c[1];
+    z = c[2];
+}
+
+// Band slots of the 8 stencil nodes of each sorted sample; at a run head the
+// run's start, whether it continues the cell of the run before it (a cut at a
+// window boundary only), and, for the first run of a cell, the run feeding
+// each of the cell's stencil nodes (band_src[d][slot]).  The run after the
+// last gets start n and continuation 0, which ends the readers' loops.
+__global__ void k_mk_slots(MarkerGeom mg, int64_t n, const float *__restrict__ pos,
+                           const unsigned long long *__restrict__ mask, const int32_t *__restrict__ start,
+                           const int32_t *__restrict__ head, const int32_t *__restrict__ rid, int32_t *__restrict__ slot,
+                           int32_t *__restrict__ run_start, uint8_t *__restrict__ run_cont,
+                           int32_t *__restrict__ band_src, int64_t bstride)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int32_t sl[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        int x, y, z;
+        stencil_node(mg, pos, n, k, d, x, y, z);
+        const int64_t w = ((int64_t)z * mg.ny + y) * mg.ntx + x / SEG;
+        const int bit = x % SEG;
+        sl[d] = start[w] + __popcll(mask[w] & ((1ull << bit) - 1ull));
+        slot[(int64_t)d * n + k] = sl[d];
+    }
+    if (head[k]) {
+        const int32_t r = rid[k];
+        const bool cont = k > 0 && floorf(pos[k]) == floorf(pos[k - 1]) &&
+                          floorf(pos[n + k]) == floorf(pos[n + k - 1]) &&
+                          floorf(pos[2 * n + k]) == floorf(pos[2 * n + k - 1]);
+        run_start[r] = (int32_t)k;
+        run_cont[r] = cont ? 1 : 0;
+        if (!cont)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) band_src[(int64_t)d * bstride + sl[d]] = r;
+    }
+    if (k == n - 1) {
+        const int32_t nr = rid[k] + head[k];
+        run_start[nr] = (int32_t)n;
+        run_cont[nr] = 0;
+    }
 }
 
 // Body copy of the caller's samples (input order); NULL ub / area / gain take
@@ -283,8 +554,12 @@ struct Pose {
 // one rounding per operation, in the order o_a + ((R_a0 X + R_a1 Y) + R_a2 Z),
 // then rounded to FP32, so the base cells do not depend on the compiler's
 // choice of fused operations; u_b = R ub + v + w x (x - o) with the FP32 x.
-__global__ void k_pose(int64_t n, const Pose P, const float *__restrict__ bx, const float *__restrict__ bu,
-                       float *__restrict__ wx, float *__restrict__ wu)
+// A sample placed outside the domain is counted in `bad` and clamped into it,
+// so that the set-up kernels after this one stay in range whether or not the
+// host waits for the count (the pose is refused either way).
+__global__ void k_pose(MarkerGeom mg, int64_t n, const Pose P, const float *__restrict__ bx,
+                       const float *__restrict__ bu, float *__restrict__ wx, float *__restrict__ wu,
+                       int *__restrict__ bad)
 {
 #pragma clang fp contract(off)
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -292,10 +567,16 @@ __global__ void k_pose(int64_t n, const Pose P, const float *__restrict__ bx, co
     const double X[3] = {(double)bx[s], (double)bx[n + s], (double)bx[2 * n + s]};
     const double U[3] = {(double)bu[s], (double)bu[n + s], (double)bu[2 * n + s]};
     double r[3], ru[3];
+    bool out = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double p = P.o[a] + ((P.R[3 * a] * X[0] + P.R[3 * a + 1] * X[1]) + P.R[3 * a + 2] * X[2]);
-        const float pf = (float)p;
+        float pf = (float)p;
+        const float top = domain_top(mg, a);
+        if (!(pf >= 0.0f) || !(pf < top)) {
+            out = true;
+            pf = top > 0.0f ? fminf(fmaxf(pf, 0.0f), __int_as_float(__float_as_int(top) - 1)) : 0.0f;
+        }
         wx[a * n + s] = pf;
         r[a] = (double)pf - P.o[a];
         ru[a] = (P.R[3 * a] * U[0] + P.R[3 * a + 1] * U[1]) + P.R[3 * a + 2] * U[2];
@@ -303,143 +584,45 @@ __global__ void k_pose(int64_t n, const Pose P, const float *__restrict__ bx, co
     wu[s] = (float)(ru[0] + P.v[0] + (P.w[1] * r[2] - P.w[2] * r[1]));
     wu[n + s] = (float)(ru[1] + P.v[1] + (P.w[2] * r[0] - P.w[0] * r[2]));
     wu[2 * n + s] = (float)(ru[2] + P.v[2] + (P.w[0] * r[1] - P.w[1] * r[0]));
+    if (out) atomicAdd(bad, 1);
 }
 
-__device__ __forceinline__ void stencil_node(const MarkerGeom &mg, const float *pos, int64_t n, int64_t k, int d, int &x,
-                                             int &y, int &z)
+// Body-frame bounding box of the samples (one workgroup): lo[3], hi[3], and
+// a flag for a non-finite coordinate.
+__global__ void __launch_bounds__(256) k_body_bounds(int64_t n, const float *__restrict__ X, float *__restrict__ out)
 {
-    const int nn[3] = {mg.nx, mg.ny, mg.nz};
-    int c[3];
+    __shared__ float sh[6][256];
+    __shared__ int nonfinite;
+    if (threadIdx.x == 0) nonfinite = 0;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    __syncthreads();
+    for (int64_t s = threadIdx.x; s < n; s += blockDim.x)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float v = X[a * n + s];
+            if (!isfinite(v)) bad = true;
+            lo[a] = fminf(lo[a], v);
+            hi[a] = fmaxf(hi[a], v);
+        }
+    if (bad) atomicOr(&nonfinite, 1);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int v = (int)floorf(pos[a * n + k]) + ((d >> a) & 1);
-        if (v >= nn[a]) v -= nn[a];
-        c[a] = v;
+        sh[a][threadIdx.x] = lo[a];
+        sh[3 + a][threadIdx.x] = hi[a];
     }
-    x = c[0];
-    y = c[1];
-    z = c[2];
-}
-
-// Marks the 2x2x2 stencil nodes of every sample in the tile bit masks.  The
-// samples are sorted, so those of one base cell are adjacent: only the first
-// of them marks (the others would set the same 8 bits), which keeps the
-// atomics per tile word down to a few.
-__global__ void k_mk_mark(MarkerGeom mg, int64_t n, const float *__restrict__ pos, unsigned long long *__restrict__ mask)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    if (k > 0 && floorf(pos[k]) == floorf(pos[k - 1]) && floorf(pos[n + k]) == floorf(pos[n + k - 1]) &&
-        floorf(pos[2 * n + k]) == floorf(pos[2 * n + k - 1]))
-        return;
-    for (int d = 0; d < 8; ++d) {
-        int x, y, z;
-        stencil_node(mg, pos, n, k, d, x, y, z);
-        const int64_t w = ((int64_t)z * mg.ny + y) * mg.ntx + x / SEG;
-        atomicOr(mask + w, 1ull << (x % SEG));
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                sh[a][threadIdx.x] = fminf(sh[a][threadIdx.x], sh[a][threadIdx.x + h]);
+                sh[3 + a][threadIdx.x] = fmaxf(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + h]);
+            }
+        __syncthreads();
     }
-}
-
-__global__ void k_tile_count(int64_t W, const unsigned long long *__restrict__ mask, int32_t *__restrict__ cnt)
-{
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w < W) cnt[w] = __popcll(mask[w]);
-}
-
-__global__ void k_band_list(MarkerGeom mg, int64_t W, const unsigned long long *__restrict__ mask,
-                            const int32_t *__restrict__ start, int32_t *__restrict__ band_cell)
-{
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= W) return;
-    unsigned long long m = mask[w];
-    if (!m) return;
-    const int xs = (int)(w % mg.ntx);
-    const int64_t row = w / mg.ntx;
-    int r = start[w];
-    while (m) {
-        const int bit = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        band_cell[r++] = (int32_t)(row * mg.nx + xs * SEG + bit);
-    }
-}
-
-__global__ void k_mk_slots(MarkerGeom mg, int64_t n, const float *__restrict__ pos,
-                           const unsigned long long *__restrict__ mask, const int32_t *__restrict__ start,
-                           int32_t *__restrict__ slot)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    for (int d = 0; d < 8; ++d) {
-        int x, y, z;
-        stencil_node(mg, pos, n, k, d, x, y, z);
-        const int64_t w = ((int64_t)z * mg.ny + y) * mg.ntx + x / SEG;
-        const int bit = x % SEG;
-        slot[(int64_t)d * n + k] = start[w] + __popcll(mask[w] & ((1ull << bit) - 1ull));
-    }
-}
-
-// runs of sorted samples that share a base cell (slot of stencil offset 0)
-// A run starts where the base cell changes (slot of stencil offset 0) and at
-// every multiple of 64 sorted samples (the window of one spreading wavefront).
-__global__ void k_run_heads(int64_t n, const int32_t *__restrict__ slot0, int32_t *__restrict__ head)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) head[k] = ((k & 63) == 0 || slot0[k] != slot0[k - 1]) ? 1 : 0;
-}
-
-// run starts, and whether a run continues the cell of the run before it
-// (cut at a window boundary only)
-__global__ void k_run_start(int64_t n, const int32_t *__restrict__ head, const int32_t *__restrict__ run_id,
-                            const int32_t *__restrict__ slot0, int32_t *__restrict__ run_start,
-                            uint8_t *__restrict__ run_cont)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    if (head[k]) {
-        run_start[run_id[k]] = (int32_t)k;
-        run_cont[run_id[k]] = (k > 0 && slot0[k] == slot0[k - 1]) ? 1 : 0;
-    }
-    if (k == n - 1) run_start[run_id[k] + head[k]] = (int32_t)n;
-}
-
-__global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) p[k] = v;
-}
-
-// band node t = base(run r) + d is fed by run r through offset d (one base
-// per target and offset, so no two runs write the same entry)
-// counts[0] = band nodes, counts[1] = runs: found on the device so that the
-// set-up reads both back with one copy at its end
-__global__ void k_counts(int64_t W, const int32_t *__restrict__ tile_start, const int32_t *__restrict__ tile_cnt,
-                         int64_t n, const int32_t *__restrict__ run_id, const int32_t *__restrict__ head,
-                         int32_t *__restrict__ counts)
-{
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        counts[0] = tile_start[W - 1] + tile_cnt[W - 1];
-        counts[1] = run_id[n - 1] + head[n - 1];
-    }
-}
-
-// band_src = -1 over its first 8 * counts[0] entries (grid-stride)
-__global__ void k_clear_band_src(int32_t *__restrict__ band_src, const int32_t *__restrict__ counts)
-{
-    const int64_t total = 8 * (int64_t)counts[0];
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x)
-        band_src[k] = -1;
-}
-
-// band_src[d][j] = the first run of the cell whose stencil offset d is band node j
-__global__ void k_band_src(int64_t n, const int32_t *__restrict__ counts, const int32_t *__restrict__ run_start,
-                           const uint8_t *__restrict__ run_cont, const int32_t *__restrict__ slot,
-                           int32_t *__restrict__ band_src)
-{
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nband = counts[0], nruns = counts[1];
-    if (r >= nruns || run_cont[r]) return;
-    const int64_t k0 = run_start[r];
-    for (int d = 0; d < 8; ++d) band_src[(int64_t)d * nband + slot[(int64_t)d * n + k0]] = (int32_t)r;
+    if (threadIdx.x < 6) out[threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x == 6) out[6] = nonfinite ? 1.0f : 0.0f;
 }
 
 __global__ void k_flags_band(MarkerGeom mg, int64_t N, const unsigned long long *__restrict__ mask,
@@ -635,31 +818,20 @@ static MarkerGeom marker_geom(const lbm_ctx *c)
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Sample sort: hipcub's stable radix sort, which at these sizes (below 2^20
-// items) runs as a block sort plus merge passes.  Forcing its onesweep radix
-// passes instead was measured slower on MI355X for 273k 8-byte keys (about
-// 165 us against 120 us per sort).
-static hipError_t sort_samples(void *tmp, size_t &tmp_bytes, const unsigned long long *keys_in,
-                               unsigned long long *keys_out, const int32_t *idx_in, int32_t *idx_out, int64_t n,
-                               int bits, hipStream_t st)
+static int64_t block_count(const lbm_ctx *c)
 {
-    return hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys_in, keys_out, idx_in, idx_out, (int)n, 0, bits,
-                                              st);
+    return (int64_t)((c->g.nx + ELL - 1) / ELL) * ((c->g.ny + ELL - 1) / ELL) * ((c->g.nz + ELL - 1) / ELL);
 }
 
-static int key_bits(const lbm_ctx *c)
-{
-    const int64_t nb = (int64_t)((c->g.nx + ELL - 1) / ELL) * ((c->g.ny + ELL - 1) / ELL) * ((c->g.nz + ELL - 1) / ELL);
-    int bits = 1;
-    while (bits < 40 && (1ll << bits) < nb) ++bits;
-    return 30 + bits;
-}
+int64_t band_capacity(const lbm_ctx *c, int64_t n) { return std::min<int64_t>(8 * std::max<int64_t>(n, 1), c->N); }
 
 hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
 {
     const size_t un = (size_t)(n > 0 ? n : 1);
     const size_t W = (size_t)c->g.W;
-    const size_t nbmax = std::min<size_t>(8 * un, (size_t)c->N);
+    const size_t nb = (size_t)block_count(c);
+    if (nb >= (size_t(1) << 31)) return hipErrorInvalidValue;  // block index of the sort key
+    const size_t nbmax = (size_t)band_capacity(c, n);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t r = o;
@@ -672,22 +844,26 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
     L->gain = take(un * 4);
     L->slot = take(8 * un * 4);
     L->cell = take(un * 4);
+    L->cell2 = take(un * 4);
     L->perm = take(un * 4);
-    L->keys_in = take(un * 8);
-    L->keys_out = take(un * 8);
-    L->idx_in = take(un * 4);
-    size_t sort_bytes = 0;
-    hipError_t e = sort_samples(nullptr, sort_bytes, nullptr, nullptr, nullptr, nullptr, (int64_t)un, key_bits(c),
-                                nullptr);
-    if (e != hipSuccess) return e;
-    L->sort_tmp_bytes = sort_bytes;
-    L->sort_tmp = take(sort_bytes);
+    L->keys = take(un * 8);
+    L->tkk = take(un * 8);
+    L->tb = take(un * 4);
+    L->bcount = take((nb + 1) * 4);
+    L->bstart = take((nb + 1) * 4);
+    L->big = take((un / RANK_MAX + 1) * 4);
+    L->occ = take(W * 8);
     L->tile_mask = take(W * 8);
-    L->tile_start = take(W * 4);
-    L->tile_count = take(W * 4);
+    // run heads followed by the tile counts, and their one exclusive scan:
+    // run ids followed by the tile starts (offset by the run count until
+    // k_band_list subtracts it)
+    L->run_head = take((un + W) * 4);
+    L->tile_count = L->run_head + un * 4;
+    L->run_id = take((un + W) * 4);
+    L->tile_start = L->run_id + un * 4;
     size_t scan_bytes = 0;
-    e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int32_t *)nullptr, (int32_t *)nullptr,
-                                         (int)std::max<size_t>(W, un));
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int32_t *)nullptr, (int32_t *)nullptr,
+                                                    (int)std::max<size_t>(un + W, nb + 1));
     if (e != hipSuccess) return e;
     L->scan_tmp_bytes = scan_bytes;
     L->scan_tmp = take(scan_bytes);
@@ -695,13 +871,10 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
     L->band_ru = take(nbmax * 4 * c->rsize);
     L->band_force = take(nbmax * 4 * c->rsize);
     L->ib_part = take(((un + 255) / 256) * 8 * 8);
-    L->run_head = take(un * 4);
-    L->run_id = take(un * 4);
     L->run_start = take((un + 1) * 4);
-    L->run_cont = take(un);
+    L->run_cont = take(un + 1);
     L->run_sum = take(8 * un * 4 * c->rsize);
     L->band_src = take(8 * nbmax * 4);
-    L->cell2 = take(un * 4);
     L->body_xyz = take(3 * un * 4);
     L->body_ub = take(3 * un * 4);
     L->body_area = take(un * 4);
@@ -713,87 +886,102 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
     return hipSuccess;
 }
 
+// misc block: [0] out-of-domain count, [16] band and run counts, [32] count
+// of buckets above RANK_MAX, [64] body box (7 floats)
+static int *misc_bad(lbm_ctx *c, const SolidsLayout &L) { return reinterpret_cast<int *>(c->mws + L.misc); }
+
 hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area, const float *gain,
-                        int *bad_host)
+                        bool posed, bool wait, int *bad_host)
 {
     SolidsLayout L;
     hipError_t e = solids_layout(c, n, &L);
     if (e != hipSuccess) return e;
     char *m = c->mws;
     const MarkerGeom mg = marker_geom(c);
-    auto *keys_in = reinterpret_cast<unsigned long long *>(m + L.keys_in);
-    auto *keys_out = reinterpret_cast<unsigned long long *>(m + L.keys_out);
-    auto *idx_in = reinterpret_cast<int32_t *>(m + L.idx_in);
-    auto *perm = reinterpret_cast<int32_t *>(m + L.perm);
+    const int64_t W = c->g.W, nb = block_count(c);
+    auto I32 = [&](size_t off) { return reinterpret_cast<int32_t *>(m + off); };
+    auto *keys = reinterpret_cast<unsigned long long *>(m + L.keys);
+    auto *tkk = reinterpret_cast<unsigned long long *>(m + L.tkk);
+    auto *tb = reinterpret_cast<uint32_t *>(m + L.tb);
+    auto *occ = reinterpret_cast<unsigned long long *>(m + L.occ);
+    int32_t *bcount = I32(L.bcount), *bstart = I32(L.bstart), *big = I32(L.big), *perm = I32(L.perm);
     int32_t *cell = c->m_cell_next;  // the current base cells stay intact until the samples pass the checks
-    int *bad = reinterpret_cast<int *>(m + L.misc);
-    int32_t *counts = reinterpret_cast<int32_t *>(m + L.misc + 16);  // band nodes, runs
+    int *bad = misc_bad(c, L);
+    int32_t *counts = I32(L.misc + 16), *nbig = I32(L.misc + 32);
     hipStream_t st = c->stream;
 
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, bad);
-    hipLaunchKernelGGL(k_mk_keys, grid_for(n), dim3(256), 0, st, mg, n, xyz, keys_in, idx_in, cell, bad);
+    // A placement counted its out-of-domain samples already (k_pose).
+    if (!posed) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, bad);
+    hipLaunchKernelGGL(k_mk_keys, grid_for(n), dim3(256), 0, st, mg, n, xyz, keys, cell, bcount, bad, occ, W, nbig);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    if (*bad) return hipSuccess;
-
-    size_t sort_bytes = L.sort_tmp_bytes;
-    e = sort_samples(m + L.sort_tmp, sort_bytes, keys_in, keys_out, idx_in, perm, n, key_bits(c), st);
+    *bad_host = 0;
+    if (wait) {
+        if ((e = hipMemcpyAsync(bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        if (*bad_host) return launch_zero(c, bcount, (size_t)(nb + 1) * 4);  // the histogram holds the others
+    }
+    // bucket sort (one bucket per l^3 block)
+    size_t scan_bytes = L.scan_tmp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(m + L.scan_tmp, scan_bytes, bcount, bstart, (int)(nb + 1), st);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter, grid_for(n), dim3(256), 0, st, n, keys, bstart, bcount, tb, tkk);
+    hipLaunchKernelGGL(k_bucket_rank, grid_for(n), dim3(256), 0, st, n, bstart, tb, tkk, perm, big, nbig);
+    hipLaunchKernelGGL(k_bucket_big, dim3(BIG_SORT_BLOCKS), dim3(1024), 0, st, bstart, big, nbig, tkk, perm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
     c->m_pos = reinterpret_cast<float *>(m + L.pos);
     c->m_ub = reinterpret_cast<float *>(m + L.ub);
     c->m_area = reinterpret_cast<float *>(m + L.area);
     c->m_gain = reinterpret_cast<float *>(m + L.gain);
-    c->m_slot = reinterpret_cast<int32_t *>(m + L.slot);
+    c->m_slot = I32(L.slot);
     c->m_cell_next = c->m_cell;
     c->m_cell = cell;
     c->m_perm = perm;
     c->tile_mask = reinterpret_cast<uint64_t *>(m + L.tile_mask);
-    c->tile_start = reinterpret_cast<int32_t *>(m + L.tile_start);
-    c->band_cell = reinterpret_cast<int32_t *>(m + L.band_cell);
+    c->tile_start = I32(L.tile_start);
+    c->band_cell = I32(L.band_cell);
     c->band_ru = m + L.band_ru;
     c->band_force = m + L.band_force;
     c->ib_part = reinterpret_cast<double *>(m + L.ib_part);
-    hipLaunchKernelGGL(k_mk_gather, grid_for(n), dim3(256), 0, st, n, perm, xyz, ub, area, gain, c->m_pos, c->m_ub,
-                       c->m_area, c->m_gain);
-    if ((e = launch_zero(c, c->tile_mask, (size_t)c->g.W * 8)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mk_mark, grid_for(n), dim3(256), 0, st, mg, n, c->m_pos,
-                       reinterpret_cast<unsigned long long *>(c->tile_mask));
-    int32_t *cnt = reinterpret_cast<int32_t *>(m + L.tile_count);
-    hipLaunchKernelGGL(k_tile_count, grid_for(c->g.W), dim3(256), 0, st, c->g.W,
-                       reinterpret_cast<const unsigned long long *>(c->tile_mask), cnt);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    size_t scan_bytes = L.scan_tmp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(m + L.scan_tmp, scan_bytes, cnt, c->tile_start, (int)c->g.W, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_band_list, grid_for(c->g.W), dim3(256), 0, st, mg, c->g.W,
-                       reinterpret_cast<const unsigned long long *>(c->tile_mask), c->tile_start, c->band_cell);
-    hipLaunchKernelGGL(k_mk_slots, grid_for(n), dim3(256), 0, st, mg, n, c->m_pos,
-                       reinterpret_cast<const unsigned long long *>(c->tile_mask), c->tile_start, c->m_slot);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // runs of samples with one base cell, and the run feeding each band node
-    int32_t *head = reinterpret_cast<int32_t *>(m + L.run_head);
-    int32_t *rid = reinterpret_cast<int32_t *>(m + L.run_id);
-    c->run_start = reinterpret_cast<int32_t *>(m + L.run_start);
-    c->run_id = rid;
+    c->run_start = I32(L.run_start);
+    c->run_id = I32(L.run_id);
     c->run_cont = reinterpret_cast<uint8_t *>(m + L.run_cont);
     c->run_sum = m + L.run_sum;
-    c->band_src = reinterpret_cast<int32_t *>(m + L.band_src);
-    hipLaunchKernelGGL(k_run_heads, grid_for(n), dim3(256), 0, st, n, c->m_slot, head);
-    scan_bytes = L.scan_tmp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(m + L.scan_tmp, scan_bytes, head, rid, (int)n, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_run_start, grid_for(n), dim3(256), 0, st, n, head, rid, c->m_slot, c->run_start, c->run_cont);
-    hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, st, c->g.W, c->tile_start, cnt, n, rid, head, counts);
-    hipLaunchKernelGGL(k_clear_band_src, dim3(1024), dim3(256), 0, st, c->band_src, counts);
-    hipLaunchKernelGGL(k_band_src, grid_for(n), dim3(256), 0, st, n, counts, c->run_start, c->run_cont, c->m_slot,
-                       c->band_src);
+    c->band_src = I32(L.band_src);
+    c->nbcap = band_capacity(c, n);
+    c->dcounts = counts;
+    c->dbad = bad;
+    auto *mask = reinterpret_cast<unsigned long long *>(c->tile_mask);
+    int32_t *head = I32(L.run_head), *cnt = I32(L.tile_count);
+
+    hipLaunchKernelGGL(k_mk_gather, grid_for(n), dim3(256), 0, st, mg, n, perm, cell, xyz, ub, area, gain, c->m_pos,
+                       c->m_ub, c->m_area, c->m_gain, head, occ);
+    hipLaunchKernelGGL(k_dilate, grid_for(W), dim3(256), 0, st, mg, W, occ, mask, cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    scan_bytes = L.scan_tmp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(m + L.scan_tmp, scan_bytes, head, c->run_id, (int)(n + W), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_band_list, grid_for(W), dim3(256), 0, st, mg, W, mask, c->tile_start, c->band_cell,
+                       c->band_src, c->nbcap, n, c->run_id, head, counts);
+    hipLaunchKernelGGL(k_mk_slots, grid_for(n), dim3(256), 0, st, mg, n, c->m_pos, mask, c->tile_start, head,
+                       c->run_id, c->m_slot, c->run_start, c->run_cont, c->band_src, c->nbcap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!wait) {
+        c->counts_exact = false;  // the counts stay on the device; nband / nruns keep the last read values
+        return hipSuccess;
+    }
+    return read_counts(c);
+}
+
+hipError_t read_counts(lbm_ctx *c)
+{
     int32_t got[2];
-    if ((e = hipMemcpyAsync(got, counts, sizeof(got), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    hipError_t e = hipMemcpyAsync(got, c->dcounts, sizeof(got), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
     c->nband = got[0];
     c->nruns = got[1];
+    c->counts_exact = true;
     return hipSuccess;
 }
 
@@ -812,13 +1000,36 @@ hipError_t solids_store_body(lbm_ctx *c, int64_t n, const float *xyz, const floa
     c->b_gain = reinterpret_cast<float *>(m + L.body_gain);
     c->w_xyz = reinterpret_cast<float *>(m + L.world_xyz);
     c->w_ub = reinterpret_cast<float *>(m + L.world_ub);
+    c->dbad = misc_bad(c, L);
+    c->box_state = 0;
+    // the block histogram starts at zero; every set-up leaves it at zero
+    if ((e = launch_zero(c, m + L.bcount, (size_t)(block_count(c) + 1) * 4)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_body_store, grid_for(n), dim3(256), 0, c->stream, n, xyz, ub, area, gain, c->b_xyz, c->b_ub,
                        c->b_area, c->b_gain);
     return hipGetLastError();
 }
 
+hipError_t body_box(lbm_ctx *c)
+{
+    SolidsLayout L;
+    hipError_t e = solids_layout(c, c->nm, &L);
+    if (e != hipSuccess) return e;
+    float *out = reinterpret_cast<float *>(c->mws + L.misc + 64);
+    hipLaunchKernelGGL(k_body_bounds, dim3(1), dim3(256), 0, c->stream, c->nm, c->b_xyz, out);
+    float box[7];
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(box, out, sizeof(box), hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+    for (int a = 0; a < 3; ++a) {
+        c->box_lo[a] = box[a];
+        c->box_hi[a] = box[3 + a];
+    }
+    c->box_state = box[6] == 0.0f ? 1 : -1;
+    return hipSuccess;
+}
+
 hipError_t solids_pose(lbm_ctx *c, const double R[9], const double o[3], const double v[3], const double w[3],
-                       int *bad_host)
+                       bool wait, int *bad_host)
 {
     Pose P{};
     for (int k = 0; k < 9; ++k) P.R[k] = R[k];
@@ -828,10 +1039,12 @@ hipError_t solids_pose(lbm_ctx *c, const double R[9], const double o[3], const d
         P.w[a] = w[a];
     }
     const int64_t n = c->nm;
-    hipLaunchKernelGGL(k_pose, grid_for(n), dim3(256), 0, c->stream, n, P, c->b_xyz, c->b_ub, c->w_xyz, c->w_ub);
+    if (wait) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c->stream, c->dbad);
+    hipLaunchKernelGGL(k_pose, grid_for(n), dim3(256), 0, c->stream, marker_geom(c), n, P, c->b_xyz, c->b_ub, c->w_xyz,
+                       c->w_ub, c->dbad);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return solids_setup(c, n, c->w_xyz, c->w_ub, c->b_area, c->b_gain, bad_host);
+    return solids_setup(c, n, c->w_xyz, c->w_ub, c->b_area, c->b_gain, true, wait, bad_host);
 }
 
 __global__ void k_gather_gain(int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ gain,

@@ -39,7 +39,14 @@ struct lbm_ctx {
     double s_nu = 1, s_b = 1, s_h[4] = {1, 1, 1, 1};
     // solid samples (marker workspace, caller-owned)
     int64_t nm = 0;
-    int64_t nband = 0;
+    int64_t nband = 0;             // band nodes: exact when counts_exact, else the last count read (a launch hint)
+    int64_t nbcap = 0;             // band capacity of the marker workspace (stride of band_src)
+    bool counts_exact = true;      // nband and nruns match the device counts
+    bool pose_pending = false;     // a pose placed without waiting: its out-of-domain count is still unread
+    int32_t *dcounts = nullptr;    // device {band nodes, runs} of the last set-up
+    int *dbad = nullptr;           // device count of samples placed outside the domain
+    int box_state = 0;             // body-frame bounding box: 0 not taken, 1 valid, -1 non-finite samples
+    double box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};
     char *mws = nullptr;
     size_t mws_bytes = 0;
     float *m_pos = nullptr, *m_ub = nullptr, *m_area = nullptr, *m_gain = nullptr;  // sorted order
@@ -56,14 +63,14 @@ struct lbm_ctx {
     void *band_ru = nullptr;       // [nband] real4 (rho, u)
     void *band_force = nullptr;    // [nband] real4 (g, 0)
     double *ib_part = nullptr;     // [ceil(nruns/256)][8] per-block force and torque partials
-    int64_t nruns = 0;             // runs: samples of one base cell, cut at every 64 sorted samples
+    int64_t nruns = 0;             // runs: samples of one base cell, cut at every 64 sorted samples (as nband)
     int32_t *run_start = nullptr;  // [nruns + 1] first sorted sample of each run
     int32_t *run_id = nullptr;     // [nm] run of each sorted sample
-    uint8_t *run_cont = nullptr;   // [nruns] 1 if the run continues the cell of the run before it
+    uint8_t *run_cont = nullptr;   // [nruns + 1] 1 if the run continues the cell of the run before it (last: 0)
     bool ib_lane_per_run = false;  // spreading sums by one lane per run instead of the wavefront scan
     int spread_mode = -1;          // -1: by band size (fused_spread()), 0: k_spread pass, 1: in the fused kernel
-    void *run_sum = nullptr;       // [8][nruns] real4: a K_d g summed over the run, per stencil offset d
-    int32_t *band_src = nullptr;   // [8][nband] run feeding band node j through offset d, or -1
+    void *run_sum = nullptr;       // [8][nm] real4: a K_d g summed over run r (r < nruns), per stencil offset d
+    int32_t *band_src = nullptr;   // [8][nbcap] run feeding band node j (j < nband) through offset d, or -1
     // adjoint workspace (caller-owned)
     char *aws = nullptr;
     size_t aws_bytes = 0;
@@ -90,13 +97,15 @@ inline bool fused_spread(const lbm_ctx *c)
 
 // Marker workspace carve-up, shared by the size query and lbm_set_solids.
 struct SolidsLayout {
-    size_t pos, ub, area, gain, slot, cell, perm, keys_in, keys_out, idx_in, sort_tmp, sort_tmp_bytes;
+    size_t pos, ub, area, gain, slot, cell, cell2, perm, keys, tkk, tb, bcount, bstart, big, occ;
     size_t tile_mask, tile_start, tile_count, scan_tmp, scan_tmp_bytes, band_cell, band_ru, band_force, ib_part, misc;
     size_t run_head, run_id, run_start, run_cont, run_sum, band_src;
-    size_t cell2, body_xyz, body_ub, body_area, body_gain, world_xyz, world_ub;
+    size_t body_xyz, body_ub, body_area, body_gain, world_xyz, world_ub;
     size_t total;
 };
 hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L);
+// most band nodes n samples can mark (the stride of band_src)
+int64_t band_capacity(const lbm_ctx *c, int64_t n);
 
 // launchers (return the first HIP error)
 hipError_t launch_fused(lbm_ctx *c);
@@ -117,13 +126,19 @@ hipError_t launch_conserved_static(lbm_ctx *c, double out[4], int *flag);
 hipError_t launch_copy(lbm_ctx *c, void *dst, const void *src, size_t bytes);
 hipError_t launch_zero(lbm_ctx *c, void *dst, size_t bytes);
 hipError_t launch_scalar_io(lbm_ctx *c, float *dst, const float *src, bool to_state);
+// Sample set-up (keys, sort, band, slots, runs).  posed: a placement counted
+// the out-of-domain samples already; wait: read that count (and stop if it is
+// not zero) and the band and run counts back, else leave them on the device.
 hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area, const float *gain,
-                        int *bad_count_host);
+                        bool posed, bool wait, int *bad_count_host);
+hipError_t read_counts(lbm_ctx *c);
+// body-frame bounding box of the samples (box_lo, box_hi, box_state); waits
+hipError_t body_box(lbm_ctx *c);
 // body copy of the caller's samples (lbm_set_solids) and a rigid placement of them (lbm_set_pose)
 hipError_t solids_store_body(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area,
                              const float *gain);
 hipError_t solids_pose(lbm_ctx *c, const double R[9], const double o[3], const double v[3], const double w[3],
-                       int *bad_count_host);
+                       bool wait, int *bad_count_host);
 hipError_t launch_solid_maps(lbm_ctx *c, uint8_t *flags, int32_t *cell, int32_t *perm);
 hipError_t launch_set_gains(lbm_ctx *c, const float *gain);
 

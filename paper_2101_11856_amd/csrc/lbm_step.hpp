@@ -36,7 +36,7 @@ template <int ST> struct StepParams {
     // spreading finished inside the fused kernel (instead of k_spread): the
     // run sums of the cells that target each band node, gathered in k_spread's order
     int fused_spread;
-    int64_t nband, nruns;
+    int64_t bstride, rstride;                // strides of band_src and run_sum (their capacities)
     const int32_t *__restrict__ band_src;
     const uint8_t *__restrict__ run_cont;
     const R4 *__restrict__ run_sum;
@@ -121,14 +121,14 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
                 R gx = 0, gy = 0, gz = 0;
 #pragma unroll
                 for (int d = 0; d < 8; ++d) {
-                    int64_t src = P.band_src[(int64_t)d * P.nband + slot];
+                    int64_t src = P.band_src[(int64_t)d * P.bstride + slot];
                     if (src >= 0) {
                         for (;;) {
-                            const auto v = P.run_sum[(int64_t)d * P.nruns + src];
+                            const auto v = P.run_sum[(int64_t)d * P.rstride + src];
                             gx += v.x;
                             gy += v.y;
                             gz += v.z;
-                            if (src + 1 >= P.nruns || !P.run_cont[src + 1]) break;
+                            if (!P.run_cont[src + 1]) break;  // the entry after the last run is 0
                             ++src;
                         }
                     }
@@ -244,25 +244,26 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
 // ---------------------------------------------------------------------------
 template <int ST>
 __global__ void __launch_bounds__(256)
-    k_band(const StepParams<ST> P, const int32_t *__restrict__ band_cell, int64_t nband,
+    k_band(const StepParams<ST> P, const int32_t *__restrict__ band_cell, const int32_t *__restrict__ counts,
            typename StepParams<ST>::R4 *__restrict__ band_ru)
 {
     using R = typename Store<ST>::R;
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nband) return;
     const Geom &g = P.g;
-    const int64_t cell = band_cell[b];
-    const int x = (int)(cell % g.nx);
-    const int64_t r = cell / g.nx;
-    const int y = (int)(r % g.ny), z = (int)(r / g.ny);
-    const Macro<R> m = node_moments<ST>(P.fin, x, y, z, g, P.inlet);
-    const R rho = (R)1 + m.drho, inv = (R)1 / rho;
-    typename StepParams<ST>::R4 v;
-    v.x = rho;
-    v.y = m.jx * inv;
-    v.z = m.jy * inv;
-    v.w = m.jz * inv;
-    band_ru[b] = v;
+    const int64_t nband = counts[0];  // on the device: the set-up of a moving solid does not wait for it
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nband; b += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t cell = band_cell[b];
+        const int x = (int)(cell % g.nx);
+        const int64_t r = cell / g.nx;
+        const int y = (int)(r % g.ny), z = (int)(r / g.ny);
+        const Macro<R> m = node_moments<ST>(P.fin, x, y, z, g, P.inlet);
+        const R rho = (R)1 + m.drho, inv = (R)1 / rho;
+        typename StepParams<ST>::R4 v;
+        v.x = rho;
+        v.y = m.jx * inv;
+        v.z = m.jy * inv;
+        v.w = m.jz * inv;
+        band_ru[b] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -289,7 +290,8 @@ constexpr int64_t IB_SEG_MAX_BLOCKS = 4096;  // grid of k_ib_seg (FP64 partials 
 
 template <typename R> struct IbParams {
     using R4 = typename R4T<R>::type;
-    int64_t n, nruns, nband;
+    int64_t n, rstride;                     // samples; stride of run_sum (its capacity)
+    const int32_t *__restrict__ counts;     // device {band nodes, runs}
     const int32_t *__restrict__ run_start;  // [nruns + 1]
     const int32_t *__restrict__ run_id;     // [n] run of each sorted sample
     const float *__restrict__ pos;          // [3][n] sorted
@@ -298,7 +300,7 @@ template <typename R> struct IbParams {
     const float *__restrict__ gain;         // [n]
     const int32_t *__restrict__ slot;       // [8][n]
     const R4 *__restrict__ band_ru;
-    R4 *__restrict__ run_sum;               // [8][nruns]
+    R4 *__restrict__ run_sum;               // [8][rstride]
     double *__restrict__ part;              // [gridDim.x][8] per-block force and torque totals
     double ox, oy, oz;                      // reference point of the torque
 };
@@ -329,7 +331,7 @@ __global__ void __launch_bounds__(256) k_ib_run(const IbParams<R> P)
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = P.n;
     double tot[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // force, then torque about (ox, oy, oz)
-    if (r < P.nruns) {
+    if (r < P.counts[1]) {
         const int64_t k0 = P.run_start[r], k1 = P.run_start[r + 1];
         R4 node[8];
 #pragma unroll
@@ -379,7 +381,7 @@ __global__ void __launch_bounds__(256) k_ib_run(const IbParams<R> P)
             v.y = acc[d][1];
             v.z = acc[d][2];
             v.w = (R)0;
-            P.run_sum[(int64_t)d * P.nruns + r] = v;
+            P.run_sum[(int64_t)d * P.rstride + r] = v;
         }
     }
     block_partial6(tot, P.part);
@@ -471,7 +473,7 @@ __global__ void __launch_bounds__(256) k_ib_seg(const IbParams<R> P)
                 w.y = v[d][1];
                 w.z = v[d][2];
                 w.w = (R)0;
-                P.run_sum[(int64_t)d * P.nruns + r] = w;
+                P.run_sum[(int64_t)d * P.rstride + r] = w;
             }
         }
     }
@@ -479,31 +481,34 @@ __global__ void __launch_bounds__(256) k_ib_seg(const IbParams<R> P)
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_spread(int64_t nband, int64_t nruns, const int32_t *__restrict__ band_src,
+__global__ void __launch_bounds__(256) k_spread(const int32_t *__restrict__ counts, int64_t bstride, int64_t rstride,
+                                                const int32_t *__restrict__ band_src,
                                                 const uint8_t *__restrict__ run_cont,
                                                 const typename R4T<R>::type *__restrict__ run_sum,
                                                 typename R4T<R>::type *__restrict__ band_force)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nband) return;
-    typename R4T<R>::type g;
-    g.x = g.y = g.z = g.w = (R)0;
+    const int64_t nband = counts[0];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nband; j += (int64_t)gridDim.x * blockDim.x) {
+        typename R4T<R>::type g;
+        g.x = g.y = g.z = g.w = (R)0;
 #pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        int64_t src = band_src[(int64_t)d * nband + j];
-        if (src >= 0) {
-            // the first run of the cell, then any runs continuing it
-            for (;;) {
-                const auto v = run_sum[(int64_t)d * nruns + src];
-                g.x += v.x;
-                g.y += v.y;
-                g.z += v.z;
-                if (src + 1 >= nruns || !run_cont[src + 1]) break;
-                ++src;
+        for (int d = 0; d < 8; ++d) {
+            int64_t src = band_src[(int64_t)d * bstride + j];
+            if (src >= 0) {
+                // the first run of the cell, then any runs continuing it (the
+                // entry after the last run is 0)
+                for (;;) {
+                    const auto v = run_sum[(int64_t)d * rstride + src];
+                    g.x += v.x;
+                    g.y += v.y;
+                    g.z += v.z;
+                    if (!run_cont[src + 1]) break;
+                    ++src;
+                }
             }
         }
+        band_force[j] = g;
     }
-    band_force[j] = g;
 }
 
 // ordered sum of the per-block force and torque partials (deterministic FP64 totals);
@@ -549,8 +554,8 @@ template <int ST> StepParams<ST> make_params(lbm_ctx *c)
     P.tile_start = c->tile_start;
     P.band_force = static_cast<const typename StepParams<ST>::R4 *>(c->band_force);
     P.fused_spread = fused_spread(c) ? 1 : 0;
-    P.nband = c->nband;
-    P.nruns = c->nruns;
+    P.bstride = c->nbcap;
+    P.rstride = c->nm;
     P.band_src = c->band_src;
     P.run_cont = c->run_cont;
     P.run_sum = static_cast<const typename StepParams<ST>::R4 *>(c->run_sum);
@@ -590,19 +595,30 @@ template <int ST, int COLL> hipError_t fused_st(lbm_ctx *c)
     return hipGetLastError();
 }
 
+// Grid of the per-band-node kernels, which loop over the device's band count:
+// one lane per node when the count is known, else room for a quarter more
+// than the last count read (a moving solid's band changes little per step).
+inline unsigned band_blocks(const lbm_ctx *c)
+{
+    int64_t want = c->nband;
+    if (!c->counts_exact) want = std::min<int64_t>(c->nbcap, c->nband + c->nband / 4 + 4096);
+    const int64_t nb = (want + 255) / 256;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(nb, 1 << 20));
+}
+
 template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *ftot, bool spread)
 {
     using R = typename Store<ST>::R;
     using R4 = typename StepParams<ST>::R4;
     StepParams<ST> P = make_params<ST>(c);
     P.fin = static_cast<const typename Store<ST>::T *>(state);
-    const unsigned nb = (unsigned)((c->nband + 255) / 256);
-    hipLaunchKernelGGL((k_band<ST>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, P, c->band_cell, c->nband,
+    const unsigned nb = band_blocks(c);
+    hipLaunchKernelGGL((k_band<ST>), dim3(nb), dim3(256), 0, c->stream, P, c->band_cell, c->dcounts,
                        static_cast<R4 *>(c->band_ru));
     IbParams<R> Q{};
     Q.n = c->nm;
-    Q.nruns = c->nruns;
-    Q.nband = c->nband;
+    Q.rstride = c->nm;
+    Q.counts = c->dcounts;
     Q.run_start = c->run_start;
     Q.run_id = c->run_id;
     Q.pos = c->m_pos;
@@ -616,13 +632,14 @@ template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *f
     Q.ox = c->pose_o[0];
     Q.oy = c->pose_o[1];
     Q.oz = c->pose_o[2];
-    const int nblk = c->ib_lane_per_run ? (int)((c->nruns + 255) / 256)
+    // lane per run: the run count is on the device, at most one run per sample
+    const int nblk = c->ib_lane_per_run ? (int)((c->nm + 255) / 256)
                                         : (int)std::min<int64_t>(IB_SEG_MAX_BLOCKS, (c->nm + 255) / 256);
     if (c->ib_lane_per_run) hipLaunchKernelGGL((k_ib_run<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
     else hipLaunchKernelGGL((k_ib_seg<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
     hipLaunchKernelGGL(k_ib_total<>, dim3(1), dim3(256), 0, c->stream, c->ib_part, nblk, ftot);
     if (spread)
-        hipLaunchKernelGGL((k_spread<R>), dim3(nb > 0 ? nb : 1), dim3(256), 0, c->stream, c->nband, c->nruns,
+        hipLaunchKernelGGL((k_spread<R>), dim3(nb), dim3(256), 0, c->stream, c->dcounts, c->nbcap, c->nm,
                            c->band_src, c->run_cont, static_cast<const R4 *>(c->run_sum),
                            static_cast<R4 *>(c->band_force));
     return hipGetLastError();

@@ -178,6 +178,49 @@ def test_ib_maps_bit_exact(name, shape, faces):
     assert np.array_equal(fl, fl_ref)
 
 
+@pytest.mark.parametrize("count", [2048, 2049, 6000])
+def test_ib_maps_crowded_block(count):
+    """The sort's buckets are the 4^3 blocks of the key: up to 2048 samples a
+    bucket is ordered by counting ranks, above that by a bitonic network.
+    `count` samples packed into one block (at, just above and well above that
+    limit) beside a sphere: maps bit-exact against the oracle; FP64 steps
+    with the crowded block to round-off."""
+    nx, ny, nz = 48, 20, 18
+    faces = (IN, OUT, NS, FS, P, P)
+    say(f"ib crowded block {count}")
+    rng = np.random.default_rng(count)
+    sph = synth.fibonacci_sphere(1500, 4.0, (14.3, ny / 2 + 0.2, nz / 2 - 0.1))
+    lo = np.array([36.0, 8.0, 8.0])
+    crowd = (lo[:, None] + 3.999 * rng.random((3, count))).astype(np.float32)  # block (9, 2, 2)
+    xyz = np.concatenate([sph, crowd], axis=1)
+    n = xyz.shape[1]
+    ub = (0.01 * rng.standard_normal((3, n))).astype(np.float32)
+    area = np.concatenate([np.full(1500, 4 * np.pi * 16.0 / 1500), np.full(count, 64.0 / count)])
+    area = (area * (0.7 + 0.6 * rng.random(n))).astype(np.float32)
+    gain = (0.5 + rng.random(n)).astype(np.float32)
+    S = O.OracleSim(nx, ny, nz, 0.05, faces=faces, u_in=(0.03, 0, 0))
+    S.set_markers(xyz, ub.astype(np.float64), area.astype(np.float64), gain.astype(np.float64))
+    fl_ref, cell_ref, perm_ref = S.maps()
+    s = gpu_solver(nx, ny, nz, 0.05, storage="f64", faces=faces, u_in=(0.03, 0, 0))
+    s.set_solids(xyz, ub, area, gain)
+    fl, cell, perm = (t.cpu().numpy() for t in s.solid_maps())
+    assert np.array_equal(cell, cell_ref)
+    assert np.array_equal(perm, perm_ref)
+    assert np.array_equal(fl, fl_ref)
+    rho = 1.0 + 1e-3 * rng.standard_normal((nz, ny, nx))
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = 0.03
+    S.init_equilibrium(rho, u)
+    S.step(3)
+    r_ref, u_ref = S.macros()
+    s.init_equilibrium(rho, u)
+    s.step(3)
+    r, uu = (to_np(t) for t in s.macros())
+    e_u, e_r, e_F = rel_l2(uu, u_ref), rel_l2(r, r_ref), rel_l2(s.ib_force(), S.last_force())
+    say(f"  rel-L2 u={e_u:.3e} rho={e_r:.3e} force={e_F:.3e}")
+    assert e_u <= 1e-12 and e_r <= 1e-12 and e_F <= 1e-11
+
+
 @pytest.mark.parametrize("name,shape,faces", IB_CASES, ids=[c[0] for c in IB_CASES])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_ib_steps(name, shape, faces, storage):
