@@ -195,9 +195,9 @@ lbm_status lbm_set_solids(lbm_ctx *ctx, int64_t n, const float *xyz, const float
  * of lbm_step read them.  Any other pose first has the device count the
  * samples outside the domain (Sync), which decides the LBM_E_INVAL above.
  * Should a pose placed without waiting still put a sample outside, that
- * sample is clamped into the domain and the next lbm_ib_force,
- * lbm_ib_torque, lbm_ib_force_eval, lbm_conserved or adjoint call returns
- * LBM_E_INVAL. */
+ * sample is clamped into the domain and the next call that waits for the
+ * device (lbm_ib_force, lbm_ib_torque, lbm_ib_force_eval, lbm_conserved, an
+ * adjoint call, or an lbm_set_pose that waits) returns LBM_E_INVAL. */
 lbm_status lbm_set_pose(lbm_ctx *ctx, const double R[9], const double o[3], const double v[3], const double w[3]);
 
 /* lbm_set_solids for a moving solid: X (device float[3][n]) are body

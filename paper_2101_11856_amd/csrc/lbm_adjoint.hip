@@ -10,11 +10,13 @@
 //                  penalty (Eq. 7) reversed -> dJ/dgamma_s; interpolation
 //                  transposed = scatter into the band adjoints of (rho, u0)
 //   k_adj_band     per band node: (rho, u0) = moments of f* (Eq. 2) reversed
-//   k_adj_gather   per node: streaming transposed for plain pulls, as a
-//                  gather (each entry written once)
+//   streaming transposed, for plain pulls: lambda_j(y) = mu_j(y + c_j), a
+//                  gather that the next step's k_adj_collide performs while
+//                  it loads lambda (k_adj_gather forms lambda on its own
+//                  only when the caller reads it or seeds it)
 //   k_adj_faces    face-layer nodes: streaming transposed for the face rules
-//                  (atomic adds), with the inlet's wall-velocity term giving
-//                  dJ/du_in(y, z)
+//                  (atomic adds into the face part of lambda), with the
+//                  inlet's wall-velocity term giving dJ/du_in(y, z)
 //   k_adj_push     per node, all rules by scattering (adds to lambda; used by
 //                  the seeds, which accumulate)
 #include "lbm_adjoint.hpp"
@@ -36,8 +38,12 @@ template <int ST> struct AdjParams {
     using R4 = typename V4<R>::type;
     Geom g;
     const T *__restrict__ fin;  // forward state f(n)
-    const R *__restrict__ lam;  // lambda(n+1), population layout
-    R *__restrict__ M;          // mu, population layout
+    // lambda(n+1), population layout: all of it, or (pending) its face-rule
+    // part, which the kernel reads and clears near the non-periodic faces
+    R *__restrict__ lam;
+    const R *__restrict__ Mprev;  // pending: mu of the step after, gathered
+    int pending;
+    R *__restrict__ M;            // mu, population layout
     Rates<R> rt;
     R body[3];
     Inlet<R> inlet;
@@ -54,6 +60,43 @@ __device__ __forceinline__ void node_of_item(const Geom &g, int64_t w, int lane,
     y = (int)(row % g.ny);
     z = (int)(row / g.ny);
     x = xs * SEG + lane;
+}
+
+// Node reached from (x, y, z) by one lattice step c along an axis (c = -1, 0,
+// +1), wrapped on a periodic axis, or -1 beyond a non-periodic face.
+__device__ __forceinline__ int step_coord(int v, int c, int n, bool periodic)
+{
+    const int t = v + c;
+    if (t >= 0 && t < n) return t;
+    return periodic ? (t < 0 ? n - 1 : 0) : -1;
+}
+
+// lambda_j at (x, y, z) from the plain pulls transposed: mu_j of the node
+// y + c_j that pulls f_j(y), or 0 when that node lies beyond a face.
+template <typename R>
+__device__ __forceinline__ void gather_plain(R (&lam)[3][3][3], const R *__restrict__ M, const Geom &g, int x, int y,
+                                             int z)
+{
+    const bool px = g.face[0] == LBM_PERIODIC, py = g.face[2] == LBM_PERIODIC, pz = g.face[4] == LBM_PERIODIC;
+    const int xd[3] = {step_coord(x, -1, g.nx, px), x, step_coord(x, 1, g.nx, px)};
+    const int yd[3] = {step_coord(y, -1, g.ny, py), y, step_coord(y, 1, g.ny, py)};
+    const int zd[3] = {step_coord(z, -1, g.nz, pz), z, step_coord(z, 1, g.nz, pz)};
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const int tx = xd[CX[j] + 1], ty = yd[CY[j] + 1], tz = zd[CZ[j] + 1];
+        R v = (R)0;
+        if (tx >= 0 && ty >= 0 && tz >= 0) v = M[(int64_t)j * g.plane + row_off(g, ty, tz) + tx];
+        lam[CZ[j] + 1][CY[j] + 1][CX[j] + 1] = v;
+    }
+}
+
+// Nodes where a face rule can send a pull's adjoint: within one node of a
+// non-periodic face (the rules read the node itself or a neighbour).
+__device__ __forceinline__ bool near_face(const Geom &g, int x, int y, int z)
+{
+    return (g.face[0] != LBM_PERIODIC && (x <= 1 || x >= g.nx - 2)) ||
+           (g.face[2] != LBM_PERIODIC && (y <= 1 || y >= g.ny - 2)) ||
+           (g.face[4] != LBM_PERIODIC && (z <= 1 || z >= g.nz - 2));
 }
 
 // FP32 arithmetic forms: capped at 128 VGPRs (4 waves per SIMD instead of 3). The band variant
@@ -89,8 +132,22 @@ k_adj_collide(const AdjParams<ST> P)
     }
     const int64_t base = row_off(g, y, z) + xc;
     R lam[3][3][3];
+    if (P.pending) {
+        // lambda = plain pulls transposed (gather of the next step's mu) +
+        // the face-rule part, which is then cleared for the next face pass
+        gather_plain(lam, P.Mprev, g, xc, y, z);
+        if (near_face(g, xc, y, z)) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) lam[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = P.lam[(int64_t)i * g.plane + base];
+            for (int i = 0; i < Q; ++i) {
+                R *e = P.lam + (int64_t)i * g.plane + base;
+                lam[CZ[i] + 1][CY[i] + 1][CX[i] + 1] += *e;
+                if (active) *e = (R)0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lam[CZ[i] + 1][CY[i] + 1][CX[i] + 1] = P.lam[(int64_t)i * g.plane + base];
+    }
     R Fb[3] = {0, 0, 0};
     if constexpr (UNIT) collide_unit_high_vjp(f, Fx, Fy, Fz, P.rt, lam, Fb[0], Fb[1], Fb[2]);
     else collide_vjp(f, Fx, Fy, Fz, P.rt, lam, Fb[0], Fb[1], Fb[2]);
@@ -169,11 +226,13 @@ __global__ void __launch_bounds__(256) k_adj_ib(const AdjIbParams<R> P)
     }
 }
 
-// Band nodes: (rho, u0) = (1 + sum d*, j / rho) reversed into mu.
+// Band nodes: (rho, u0) = (1 + sum d*, j / rho) reversed into mu.  Each
+// lane clears its band_bar entry after reading it, so that the scatter of the
+// next reverse step (k_adj_ib) starts from zeros without a fill launch.
 template <typename R>
 __global__ void __launch_bounds__(256) k_adj_band(Geom g, const int32_t *__restrict__ band_cell, int64_t nband,
                                                   const typename V4<R>::type *__restrict__ band_ru,
-                                                  const typename V4<R>::type *__restrict__ band_bar, R *__restrict__ M)
+                                                  typename V4<R>::type *__restrict__ band_bar, R *__restrict__ M)
 {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nband) return;
@@ -183,6 +242,7 @@ __global__ void __launch_bounds__(256) k_adj_band(Geom g, const int32_t *__restr
     const int y = (int)(r % g.ny), z = (int)(r / g.ny);
     const auto ru = band_ru[b];
     const auto bb = band_bar[b];
+    band_bar[b] = typename V4<R>::type{(R)0, (R)0, (R)0, (R)0};
     const R inv = (R)1 / ru.x;
     const int64_t base = row_off(g, y, z) + x;
 #pragma unroll
@@ -222,10 +282,12 @@ __global__ void __launch_bounds__(256) k_adj_push(Geom g, const R *__restrict__ 
 }
 
 // Streaming transposed for a whole step, in two parts.
-// Plain part (gather, overwrites lambda): a value f_j(y) read by a plain pull
-// (source inside the domain, periodic axes wrapped) is read by node y + c_j
-// only, so lambda_j(y) = mu_j(y + c_j) when that node exists, else 0.  No
-// atomics: each entry is written once.
+// Plain part: a value f_j(y) read by a plain pull (source inside the domain,
+// periodic axes wrapped) is read by node y + c_j only, so lambda_j(y) =
+// mu_j(y + c_j) when that node exists, else 0: a gather, which the next
+// reverse step's k_adj_collide does as it loads lambda.  k_adj_gather forms
+// lambda = gather + (face part already in lam) in place, for the calls that
+// need lambda itself (lbm_adjoint_get, the seeds).
 template <typename R>
 __global__ void __launch_bounds__(256) k_adj_gather(Geom g, const R *__restrict__ M, R *__restrict__ lam)
 {
@@ -236,27 +298,17 @@ __global__ void __launch_bounds__(256) k_adj_gather(Geom g, const R *__restrict_
     wave_coords(w, g, xs, y, z);
     const int x = xs * SEG + lane;
     if (x >= g.nx) return;
-    const bool px = g.face[0] == LBM_PERIODIC, py = g.face[2] == LBM_PERIODIC, pz = g.face[4] == LBM_PERIODIC;
-    // destination coordinate along one axis (c = +1 / -1), or -1 if it lies beyond a non-periodic face
-    auto step = [](int v, int c, int n, bool periodic) {
-        const int t = v + c;
-        if (t >= 0 && t < n) return t;
-        return periodic ? (t < 0 ? n - 1 : 0) : -1;
-    };
-    const int xd[3] = {step(x, -1, g.nx, px), x, step(x, 1, g.nx, px)};
-    const int yd[3] = {step(y, -1, g.ny, py), y, step(y, 1, g.ny, py)};
-    const int zd[3] = {step(z, -1, g.nz, pz), z, step(z, 1, g.nz, pz)};
+    R v[3][3][3];
+    gather_plain(v, M, g, x, y, z);
     const int64_t base = row_off(g, y, z) + x;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-        const int tx = xd[CX[j] + 1], ty = yd[CY[j] + 1], tz = zd[CZ[j] + 1];
-        R v = (R)0;
-        if (tx >= 0 && ty >= 0 && tz >= 0) v = M[(int64_t)j * g.plane + row_off(g, ty, tz) + tx];
-        lam[(int64_t)j * g.plane + base] = v;
+        R *e = lam + (int64_t)j * g.plane + base;
+        *e = v[CZ[j] + 1][CY[j] + 1][CX[j] + 1] + *e;
     }
 }
 
-// Face part (adds to lambda after k_adj_gather): every pull (i, x) whose source
+// Face part (adds to the face part of lambda): every pull (i, x) whose source
 // lies beyond a non-periodic face (bounce-back, inlet, outflow, free slip)
 // adds mu_i(x) to the adjoint of the population the face rule read; the inlet
 // term adds mu_i 2 w_i c_i / cs^2 to dJ/du_in.  Only face-layer nodes have such
@@ -366,9 +418,10 @@ void adjoint_bind(lbm_ctx *c, void *ws, size_t bytes)
     char *p = static_cast<char *>(ws);
     c->aws = p;
     c->aws_bytes = bytes;
-    c->lam_in = p;
-    c->lam_out = p + planes;
-    c->adjM = p + 2 * planes;
+    c->lam = p;
+    c->adjM = p + planes;
+    c->adjM2 = p + 2 * planes;
+    c->adj_pending = false;
     c->band_phi = p + 3 * planes;
     c->band_bar = p + 3 * planes + band;
     c->adj_band_cap = std::max<int64_t>(c->nband, 1);
@@ -380,8 +433,10 @@ template <int ST> static AdjParams<ST> adj_params(lbm_ctx *c, const void *state)
     AdjParams<ST> P{};
     P.g = c->g;
     P.fin = static_cast<const typename Store<ST>::T *>(state);
-    P.lam = static_cast<const R *>(c->lam_in);
-    P.M = static_cast<R *>(c->adjM);
+    P.lam = static_cast<R *>(c->lam);
+    P.Mprev = static_cast<const R *>(c->adjM);
+    P.pending = c->adj_pending ? 1 : 0;
+    P.M = static_cast<R *>(c->adjM2);
     P.rt = {(R)c->s_nu, (R)c->s_b, (R)c->s_h[0], (R)c->s_h[1], (R)c->s_h[2], (R)c->s_h[3]};
     for (int a = 0; a < 3; ++a) {
         P.body[a] = (R)c->p.body_force[a];
@@ -395,12 +450,11 @@ template <int ST> static AdjParams<ST> adj_params(lbm_ctx *c, const void *state)
     return P;
 }
 
-// IB part of the reverse sweep: band_phi -> g_gain, band_bar -> mu
+// IB part of the reverse sweep: band_phi -> g_gain, band_bar -> mu (band_bar
+// is zero on entry: cleared by lbm_adjoint_init, then by each k_adj_band)
 template <typename R> static hipError_t adj_ib_part(lbm_ctx *c, double *g_gain)
 {
     using R4 = typename V4<R>::type;
-    hipLaunchKernelGGL((k_fill4<R>), g1(c->nband), dim3(256), 0, c->stream, static_cast<R4 *>(c->band_bar), c->nband,
-                       (R)0, (R)0, (R)0, (R)0);
     AdjIbParams<R> Q{};
     Q.n = c->nm;
     Q.pos = c->m_pos;
@@ -415,8 +469,8 @@ template <typename R> static hipError_t adj_ib_part(lbm_ctx *c, double *g_gain)
     Q.g_gain = g_gain;
     hipLaunchKernelGGL((k_adj_ib<R>), g1(c->nm), dim3(256), 0, c->stream, Q);
     hipLaunchKernelGGL((k_adj_band<R>), g1(c->nband), dim3(256), 0, c->stream, c->g, c->band_cell, c->nband,
-                       static_cast<const R4 *>(c->band_ru), static_cast<const R4 *>(c->band_bar),
-                       static_cast<R *>(c->adjM));
+                       static_cast<const R4 *>(c->band_ru), static_cast<R4 *>(c->band_bar),
+                       static_cast<R *>(c->adjM2));
     return hipGetLastError();
 }
 
@@ -436,20 +490,36 @@ template <int ST> static hipError_t step_st(lbm_ctx *c, const void *state, doubl
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (c->nm > 0 && (e = adj_ib_part<R>(c, g_gain)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_adj_gather<R>), grid, block, 0, c->stream, c->g, static_cast<const R *>(c->adjM),
-                       static_cast<R *>(c->lam_out));
+    if (!c->adj_pending) {
+        // lam held all of lambda(n+1); from now on it holds the face part only
+        if ((e = launch_zero(c, c->lam, (size_t)c->g.total * c->rsize)) != hipSuccess) return e;
+    }
     const FaceSet F = face_set(c->g);
     if (F.na + F.nb > 0)
         hipLaunchKernelGGL((k_adj_faces<R>), g1(F.na + F.nb), block, 0, c->stream, c->g, F,
-                           static_cast<const R *>(c->adjM), static_cast<R *>(c->lam_out), g_inlet);
+                           static_cast<const R *>(c->adjM2), static_cast<R *>(c->lam), g_inlet);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    std::swap(c->lam_in, c->lam_out);
+    std::swap(c->adjM, c->adjM2);
+    c->adj_pending = true;  // lambda(n) = plain pulls transposed (adjM) + lam
     return hipSuccess;
+}
+
+// lambda itself in lam (after a reverse step it is the gather of adjM plus the
+// face part that lam holds)
+template <typename R> static hipError_t adj_form(lbm_ctx *c)
+{
+    if (!c->adj_pending) return hipSuccess;
+    hipLaunchKernelGGL((k_adj_gather<R>), dim3((unsigned)((c->g.W + 3) / 4)), dim3(256), 0, c->stream, c->g,
+                       static_cast<const R *>(c->adjM), static_cast<R *>(c->lam));
+    c->adj_pending = false;
+    return hipGetLastError();
 }
 
 template <int ST> static hipError_t seed_macros_st(lbm_ctx *c, const void *g_rho, const void *g_u, double *g_inlet)
 {
     using R = typename Store<ST>::R;
+    const hipError_t e = adj_form<R>(c);  // the seed adds to lambda; adjM is scratch below
+    if (e != hipSuccess) return e;
     Inlet<R> inl{};
     inl.prof = static_cast<const R *>(c->p.inlet_profile);
     for (int a = 0; a < 3; ++a) inl.u[a] = (R)c->p.u_in[a];
@@ -457,7 +527,7 @@ template <int ST> static hipError_t seed_macros_st(lbm_ctx *c, const void *g_rho
                        static_cast<const typename Store<ST>::T *>(c->fA), inl, static_cast<const R *>(g_rho),
                        static_cast<const R *>(g_u), static_cast<R *>(c->adjM), c->N);
     hipLaunchKernelGGL((k_adj_push<R>), dim3((unsigned)((c->g.W + 3) / 4)), dim3(256), 0, c->stream, c->g,
-                       static_cast<const R *>(c->adjM), static_cast<R *>(c->lam_in), g_inlet);
+                       static_cast<const R *>(c->adjM), static_cast<R *>(c->lam), g_inlet);
     return hipGetLastError();
 }
 
@@ -466,14 +536,15 @@ template <int ST> static hipError_t seed_force_st(lbm_ctx *c, const double gf[3]
     using R = typename Store<ST>::R;
     using R4 = typename V4<R>::type;
     hipError_t e;
+    if ((e = adj_form<R>(c)) != hipSuccess) return e;  // the seed adds to lambda; adjM2 is scratch below
     if ((e = launch_band_ib(c, c->fA, c->ftot_eval)) != hipSuccess) return e;
-    if ((e = launch_zero(c, c->adjM, (size_t)c->g.total * c->rsize)) != hipSuccess) return e;
+    if ((e = launch_zero(c, c->adjM2, (size_t)c->g.total * c->rsize)) != hipSuccess) return e;
     // phi = g_force at every band node: the gather sum_d K_d phi then equals g_force
     hipLaunchKernelGGL((k_fill4<R>), g1(c->nband), dim3(256), 0, c->stream, static_cast<R4 *>(c->band_phi), c->nband,
                        (R)gf[0], (R)gf[1], (R)gf[2], (R)0);
     if ((e = adj_ib_part<R>(c, g_gain)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_adj_push<R>), dim3((unsigned)((c->g.W + 3) / 4)), dim3(256), 0, c->stream, c->g,
-                       static_cast<const R *>(c->adjM), static_cast<R *>(c->lam_in), g_inlet);
+                       static_cast<const R *>(c->adjM2), static_cast<R *>(c->lam), g_inlet);
     return hipGetLastError();
 }
 
@@ -502,11 +573,17 @@ hipError_t adjoint_seed_force(lbm_ctx *c, const double g_force[3], double *g_inl
 
 hipError_t adjoint_io(lbm_ctx *c, void *dense, bool to_state)
 {
+    if (to_state) {
+        c->adj_pending = false;  // lam takes all of lambda
+    } else {
+        const hipError_t e = c->rsize == 8 ? adj_form<double>(c) : adj_form<float>(c);
+        if (e != hipSuccess) return e;
+    }
     if (c->rsize == 8)
         hipLaunchKernelGGL((k_adj_io<double>), g1(c->N), dim3(256), 0, c->stream, c->g,
-                           static_cast<double *>(c->lam_in), static_cast<double *>(dense), c->N, to_state ? 1 : 0);
+                           static_cast<double *>(c->lam), static_cast<double *>(dense), c->N, to_state ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_adj_io<float>), g1(c->N), dim3(256), 0, c->stream, c->g, static_cast<float *>(c->lam_in),
+        hipLaunchKernelGGL((k_adj_io<float>), g1(c->N), dim3(256), 0, c->stream, c->g, static_cast<float *>(c->lam),
                            static_cast<float *>(dense), c->N, to_state ? 1 : 0);
     return hipGetLastError();
 }

@@ -712,7 +712,9 @@ lbm_status lbm_adjoint_init(lbm_ctx *c, void *adj_ws, size_t bytes)
     if (bytes < adjoint_ws_bytes(c))
         return fail(c, LBM_E_NOMEM, "adjoint workspace too small: need " + std::to_string(adjoint_ws_bytes(c)) + " bytes");
     adjoint_bind(c, adj_ws, bytes);
-    HIP_TRY(c, launch_zero(c, c->lam_in, (size_t)c->g.total * c->rsize), "lbm_adjoint_init");
+    HIP_TRY(c, launch_zero(c, c->lam, (size_t)c->g.total * c->rsize), "lbm_adjoint_init");
+    if (c->band_bar)  // the IB reverse scatter accumulates into it from zero
+        HIP_TRY(c, launch_zero(c, c->band_bar, (size_t)c->adj_band_cap * 4 * c->rsize), "lbm_adjoint_init");
     return LBM_OK;
 }
 

@@ -75,7 +75,10 @@ struct lbm_ctx {
     char *aws = nullptr;
     size_t aws_bytes = 0;
     int64_t adj_band_cap = -1;     // band capacity the adjoint workspace was sized for (-1 = unbound)
-    void *lam_in = nullptr, *lam_out = nullptr, *adjM = nullptr;  // real planes like the populations
+    // real planes like the populations: lam = dJ/df (or, while adj_pending,
+    // only its face-rule part), adjM = mu of the last reverse step, adjM2 the next
+    void *lam = nullptr, *adjM = nullptr, *adjM2 = nullptr;
+    bool adj_pending = false;      // lambda = (plain pulls transposed)(adjM) + lam, not yet formed
     void *band_phi = nullptr;      // [nband] real4 adjoint of the band force
     void *band_bar = nullptr;      // [nband] real4 adjoint of (rho, u0) at band nodes
     std::string err;

@@ -243,26 +243,41 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
 // band pre-pass: streamed rho and u0 = j/rho of every band node
 // ---------------------------------------------------------------------------
 template <int ST>
-__global__ void __launch_bounds__(256)
-    k_band(const StepParams<ST> P, const int32_t *__restrict__ band_cell, const int32_t *__restrict__ counts,
-           typename StepParams<ST>::R4 *__restrict__ band_ru)
+__device__ __forceinline__ void band_node(const StepParams<ST> &P, const int32_t *__restrict__ band_cell, int64_t b,
+                                          typename StepParams<ST>::R4 *__restrict__ band_ru)
 {
     using R = typename Store<ST>::R;
     const Geom &g = P.g;
-    const int64_t nband = counts[0];  // on the device: the set-up of a moving solid does not wait for it
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nband; b += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t cell = band_cell[b];
-        const int x = (int)(cell % g.nx);
-        const int64_t r = cell / g.nx;
-        const int y = (int)(r % g.ny), z = (int)(r / g.ny);
-        const Macro<R> m = node_moments<ST>(P.fin, x, y, z, g, P.inlet);
-        const R rho = (R)1 + m.drho, inv = (R)1 / rho;
-        typename StepParams<ST>::R4 v;
-        v.x = rho;
-        v.y = m.jx * inv;
-        v.z = m.jy * inv;
-        v.w = m.jz * inv;
-        band_ru[b] = v;
+    const int64_t cell = band_cell[b];
+    const int x = (int)(cell % g.nx);
+    const int64_t r = cell / g.nx;
+    const int y = (int)(r % g.ny), z = (int)(r / g.ny);
+    const Macro<R> m = node_moments<ST>(P.fin, x, y, z, g, P.inlet);
+    const R rho = (R)1 + m.drho, inv = (R)1 / rho;
+    typename StepParams<ST>::R4 v;
+    v.x = rho;
+    v.y = m.jx * inv;
+    v.z = m.jy * inv;
+    v.w = m.jz * inv;
+    band_ru[b] = v;
+}
+
+// LOOP = false: one lane per band node, the count `known` from the host.
+// LOOP = true: the count is read on the device (the set-up of a moving solid
+// does not wait for it) and the lanes loop over it.  Two variants, because
+// the loop keeps the kernel arguments live across iterations (about 100 more
+// scalar registers spilled).
+template <int ST, bool LOOP>
+__global__ void __launch_bounds__(256)
+    k_band(const StepParams<ST> P, const int32_t *__restrict__ band_cell, int64_t known, const int32_t *__restrict__ counts,
+           typename StepParams<ST>::R4 *__restrict__ band_ru)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if constexpr (LOOP) {
+        const int64_t nband = counts[0];
+        for (int64_t b = b0; b < nband; b += (int64_t)gridDim.x * blockDim.x) band_node<ST>(P, band_cell, b, band_ru);
+    } else {
+        if (b0 < known) band_node<ST>(P, band_cell, b0, band_ru);
     }
 }
 
@@ -481,13 +496,14 @@ __global__ void __launch_bounds__(256) k_ib_seg(const IbParams<R> P)
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_spread(const int32_t *__restrict__ counts, int64_t bstride, int64_t rstride,
+__global__ void __launch_bounds__(256) k_spread(int64_t known, const int32_t *__restrict__ counts, int64_t bstride,
+                                                int64_t rstride,
                                                 const int32_t *__restrict__ band_src,
                                                 const uint8_t *__restrict__ run_cont,
                                                 const typename R4T<R>::type *__restrict__ run_sum,
                                                 typename R4T<R>::type *__restrict__ band_force)
 {
-    const int64_t nband = counts[0];
+    const int64_t nband = known >= 0 ? known : counts[0];
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nband; j += (int64_t)gridDim.x * blockDim.x) {
         typename R4T<R>::type g;
         g.x = g.y = g.z = g.w = (R)0;
@@ -613,8 +629,13 @@ template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *f
     StepParams<ST> P = make_params<ST>(c);
     P.fin = static_cast<const typename Store<ST>::T *>(state);
     const unsigned nb = band_blocks(c);
-    hipLaunchKernelGGL((k_band<ST>), dim3(nb), dim3(256), 0, c->stream, P, c->band_cell, c->dcounts,
-                       static_cast<R4 *>(c->band_ru));
+    const int64_t known = c->counts_exact ? c->nband : -1;
+    if (known >= 0)
+        hipLaunchKernelGGL((k_band<ST, false>), dim3(nb), dim3(256), 0, c->stream, P, c->band_cell, known, c->dcounts,
+                           static_cast<R4 *>(c->band_ru));
+    else
+        hipLaunchKernelGGL((k_band<ST, true>), dim3(nb), dim3(256), 0, c->stream, P, c->band_cell, known, c->dcounts,
+                           static_cast<R4 *>(c->band_ru));
     IbParams<R> Q{};
     Q.n = c->nm;
     Q.rstride = c->nm;
@@ -639,7 +660,7 @@ template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *f
     else hipLaunchKernelGGL((k_ib_seg<R>), dim3((unsigned)nblk), dim3(256), 0, c->stream, Q);
     hipLaunchKernelGGL(k_ib_total<>, dim3(1), dim3(256), 0, c->stream, c->ib_part, nblk, ftot);
     if (spread)
-        hipLaunchKernelGGL((k_spread<R>), dim3(nb), dim3(256), 0, c->stream, c->dcounts, c->nbcap, c->nm,
+        hipLaunchKernelGGL((k_spread<R>), dim3(nb), dim3(256), 0, c->stream, known, c->dcounts, c->nbcap, c->nm,
                            c->band_src, c->run_cont, static_cast<const R4 *>(c->run_sum),
                            static_cast<R4 *>(c->band_force));
     return hipGetLastError();
