@@ -133,7 +133,10 @@ lbm_status lbm_workspace_size(const lbm_params *p, size_t *bytes);
  * sample (results equal up to FP32 round-off), LBM_FUSED_SPREAD = 0 / 1
  * finishes the spreading in a separate pass / inside the fused kernel (by
  * default the fused kernel does it when the band has at most 2^20 nodes;
- * bit-identical either way).  Keep them unchanged between the two calls. */
+ * bit-identical either way), LBM_POSE_NO_WAIT = 1 makes lbm_set_pose place
+ * every pose without waiting, also one it cannot show to be inside the
+ * domain (a test of the clamping guard and the deferred LBM_E_INVAL
+ * described there).  Keep them unchanged between the two calls. */
 lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out);
 
 lbm_status lbm_set_stream(lbm_ctx *ctx, void *hip_stream);

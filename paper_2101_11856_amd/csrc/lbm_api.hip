@@ -262,6 +262,10 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, voi
         // LBM_FUSED_SPREAD = 0 / 1 forces one (for measurements)
         const char *fs = std::getenv("LBM_FUSED_SPREAD");
         c->spread_mode = fs ? (std::strtol(fs, nullptr, 10) != 0 ? 1 : 0) : -1;
+        // every pose placed without waiting, shown inside or not (a test of the
+        // device's clamping guard and of the deferred LBM_E_INVAL)
+        const char *pw = std::getenv("LBM_POSE_NO_WAIT");
+        c->pose_no_wait = pw && std::strtol(pw, nullptr, 10) != 0;
     }
     c->ws = static_cast<char *>(workspace);
     c->ws_bytes = ws_bytes;
@@ -432,27 +436,15 @@ lbm_status lbm_set_body(lbm_ctx *c, int64_t n, const float *X, const float *ub, 
 }
 
 // Whether every sample placed at (R, o) is inside the domain, shown from the
-// body-frame bounding box: interval bounds of o_a + sum_b R_ab X_b over the
-// box, widened by a margin far above the rounding of the FP64 placement and
-// of its FP32 result.  False when that cannot be shown (the device then
-// counts the samples outside).
+// body-frame bounding box (pose_inside_box); false when that cannot be shown
+// (the device then counts the samples outside).
 static bool pose_inside(const lbm_ctx *c, const double R[9], const double o[3])
 {
     if (c->box_state != 1) return false;
     const int n[3] = {c->g.nx, c->g.ny, c->g.nz};
-    for (int a = 0; a < 3; ++a) {
-        double lo = o[a], hi = o[a], mag = std::fabs(o[a]);
-        for (int b = 0; b < 3; ++b) {
-            const double p = R[3 * a + b] * c->box_lo[b], q = R[3 * a + b] * c->box_hi[b];
-            lo += std::min(p, q);
-            hi += std::max(p, q);
-            mag += std::max(std::fabs(p), std::fabs(q));
-        }
-        const double margin = (mag + 1.0) * 0x1p-20;
-        const double top = c->g.face[2 * a] == LBM_PERIODIC ? n[a] : n[a] - 1;
-        if (!(lo - margin >= 0.0) || !(hi + margin < top)) return false;
-    }
-    return true;
+    double top[3];
+    for (int a = 0; a < 3; ++a) top[a] = c->g.face[2 * a] == LBM_PERIODIC ? n[a] : n[a] - 1;
+    return pose_inside_box(R, o, c->box_lo, c->box_hi, top);
 }
 
 // Reads the device counts of a set-up that did not wait for them and, for a
@@ -483,7 +475,7 @@ lbm_status lbm_set_pose(lbm_ctx *c, const double R[9], const double o[3], const 
     if (c->box_state == 0) HIP_TRY(c, body_box(c), "lbm_set_pose");
     // Shown inside on the host: no wait (the set-up runs behind the caller's
     // queue).  Otherwise the device counts the samples outside first.
-    const bool inside = pose_inside(c, R, o);
+    const bool inside = c->pose_no_wait || pose_inside(c, R, o);
     if (!inside) {
         const lbm_status st = settle_counts(c, "lbm_set_pose");
         if (st != LBM_OK) return st;

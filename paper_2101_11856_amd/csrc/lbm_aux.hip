@@ -550,10 +550,9 @@ struct Pose {
     double R[9], o[3], v[3], w[3];  // R row-major
 };
 
-// Rigid placement (the sample update of Alg. 2 (c)): x = o + R X in FP64 with
-// one rounding per operation, in the order o_a + ((R_a0 X + R_a1 Y) + R_a2 Z),
-// then rounded to FP32, so the base cells do not depend on the compiler's
-// choice of fused operations; u_b = R ub + v + w x (x - o) with the FP32 x.
+// Rigid placement (the sample update of Alg. 2 (c)): x = o + R X by
+// place_coord (FP64, one rounding per operation, then FP32); u_b = R ub + v +
+// w x (x - o) with the FP32 x.
 // A sample placed outside the domain is counted in `bad` and clamped into it,
 // so that the set-up kernels after this one stay in range whether or not the
 // host waits for the count (the pose is refused either way).
@@ -570,8 +569,7 @@ __global__ void k_pose(MarkerGeom mg, int64_t n, const Pose P, const float *__re
     bool out = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double p = P.o[a] + ((P.R[3 * a] * X[0] + P.R[3 * a + 1] * X[1]) + P.R[3 * a + 2] * X[2]);
-        float pf = (float)p;
+        float pf = place_coord(P.R, P.o, a, X[0], X[1], X[2]);
         const float top = domain_top(mg, a);
         if (!(pf >= 0.0f) || !(pf < top)) {
             out = true;

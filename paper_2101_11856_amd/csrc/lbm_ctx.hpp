@@ -43,6 +43,7 @@ struct lbm_ctx {
     int64_t nbcap = 0;             // band capacity of the marker workspace (stride of band_src)
     bool counts_exact = true;      // nband and nruns match the device counts
     bool pose_pending = false;     // a pose placed without waiting: its out-of-domain count is still unread
+    bool pose_no_wait = false;     // LBM_POSE_NO_WAIT: place every pose without waiting (guard test)
     int32_t *dcounts = nullptr;    // device {band nodes, runs} of the last set-up
     int *dbad = nullptr;           // device count of samples placed outside the domain
     int box_state = 0;             // body-frame bounding box: 0 not taken, 1 valid, -1 non-finite samples

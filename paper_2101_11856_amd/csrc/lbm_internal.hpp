@@ -1135,4 +1135,42 @@ __device__ __forceinline__ Macro<R> node_moments(const typename Store<ST>::T *__
     return moments01(f);
 }
 
+// ---------------------------------------------------------------------------
+// rigid placement of a solid sample (the sample update of Alg. 2 (c))
+// ---------------------------------------------------------------------------
+// Coordinate a of x = o + R X (R row-major) in FP64 with one rounding per
+// operation, in the order o_a + ((R_a0 X + R_a1 Y) + R_a2 Z), then rounded to
+// FP32, so that the base cells do not depend on the compiler's choice of fused
+// operations (the same function on the host and the device).
+__host__ __device__ inline float place_coord(const double R[9], const double o[3], int a, double X, double Y, double Z)
+{
+#pragma clang fp contract(off)
+    const double p = o[a] + ((R[3 * a] * X + R[3 * a + 1] * Y) + R[3 * a + 2] * Z);
+    return (float)p;
+}
+
+// Whether every sample of a body whose body-frame coordinates lie in the box
+// [lo, hi] is placed by place_coord inside [0, top_a) on every axis: interval
+// bounds of o_a + sum_b R_ab X_b over the box, widened by (|o_a| +
+// sum_b max|R_ab X_b| + 1) 2^-20, which is far above the rounding of the
+// FP64 placement (a few units of 2^-53 of that magnitude) and of its FP32
+// result (2^-24).  False when that cannot be shown.
+inline bool pose_inside_box(const double R[9], const double o[3], const double lo[3], const double hi[3],
+                            const double top[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double l = o[a], h = o[a], mag = o[a] < 0 ? -o[a] : o[a];
+        for (int b = 0; b < 3; ++b) {
+            const double p = R[3 * a + b] * lo[b], q = R[3 * a + b] * hi[b];
+            l += p < q ? p : q;
+            h += p < q ? q : p;
+            const double ap = p < 0 ? -p : p, aq = q < 0 ? -q : q;
+            mag += ap > aq ? ap : aq;
+        }
+        const double margin = (mag + 1.0) * 0x1p-20;
+        if (!(l - margin >= 0.0) || !(h + margin < top[a])) return false;
+    }
+    return true;
+}
+
 }  // namespace lbm

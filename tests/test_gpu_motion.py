@@ -138,6 +138,44 @@ def test_rejected_pose_keeps_the_previous_one():
     assert all(torch.equal(x, y) for x, y in zip(runs[0][2], runs[1][2]))
 
 
+def test_pose_placed_without_waiting(monkeypatch):
+    """LBM_POSE_NO_WAIT=1 places every pose without waiting for the device's
+    count of samples outside the domain.  Valid poses then give the same bits
+    as the waiting path (here near a wall, where the host bound cannot show
+    them inside); a pose that puts samples outside is not refused by
+    lbm_set_pose, its samples are clamped into the domain (every kernel stays
+    in range) and the next synchronising call reports LBM_E_INVAL; after
+    that, valid poses work again."""
+    from paper_2101_11856_amd.lbm import LbmError
+    nx, ny, nz = SHAPE
+    say("pose without waiting")
+    X, ub, area, gain = _body()
+    rho, u = _flow(nx, ny, nz)
+    near_wall = np.array([0.0, -6.0, 0.0])   # lowest sample at y = 0.5: valid, beyond what the box bound shows
+    runs = []
+    for no_wait in ("0", "1"):
+        monkeypatch.setenv("LBM_POSE_NO_WAIT", no_wait)
+        s = gpu_solver(nx, ny, nz, 0.05, faces=FACES)
+        s.init_equilibrium(rho, u)
+        s.set_body(X, ub, area, gain, *_pose(0))
+        for t in range(1, 4):
+            R, o, v, w = _pose(t)
+            s.set_pose(R, o + near_wall, v, w)
+            s.step(1)
+        runs.append((s.get_populations().clone(), s.ib_torque(), s.solid_maps()))
+    assert torch.equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    assert all(torch.equal(a, b) for a, b in zip(runs[0][2], runs[1][2]))
+    # a pose with samples outside: placed, clamped, reported at the next synchronising call
+    R, o, v, w = _pose(4)
+    s.set_pose(R, o + np.array([0.0, 10.0, 0.0]), v, w)        # the upper part beyond y = ny - 1
+    s.step(1)
+    with pytest.raises(LbmError, match="clamped"):
+        s.ib_force()
+    s.set_pose(*_pose(5))
+    s.step(1)
+    assert np.all(np.isfinite(s.ib_force())) and np.all(np.isfinite(s.conserved()))
+
+
 def test_pose_needs_samples_inside_the_domain():
     from paper_2101_11856_amd.lbm import LbmError
     s = gpu_solver(16, 16, 16, 0.05, faces=FACES)
