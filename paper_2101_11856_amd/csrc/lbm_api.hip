@@ -403,7 +403,7 @@ static lbm_status set_samples(lbm_ctx *c, const char *who, int64_t n, const floa
             e = solids_pose(c, R, o, v, w, true, &bad);
             if (e != hipSuccess || bad) c->nm = 0;
         } else {
-            e = solids_setup(c, n, c->b_xyz, c->b_ub, c->b_area, c->b_gain, false, true, &bad);
+            e = solids_setup(c, n, c->b_xyz, c->b_ub, c->b_area, c->b_gain, true, &bad);
         }
     }
     if (e != hipSuccess) return hip_fail(c, e, who);

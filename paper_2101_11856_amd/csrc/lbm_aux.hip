@@ -210,7 +210,7 @@ __global__ void k_scalar_io(Geom g, float *__restrict__ dst, const float *__rest
 // ---------------------------------------------------------------------------
 constexpr int ELL = 4;
 constexpr int RANK_MAX = 2048;
-constexpr int BIG_SORT_BLOCKS = 64;
+constexpr int BIG_SORT_BLOCKS = 16;
 
 struct MarkerGeom {
     int nx, ny, nz, nbx, nby, ntx;
@@ -247,23 +247,73 @@ __device__ __forceinline__ int32_t wave_grouped_add(int32_t *p, int32_t key, int
     return mine;
 }
 
+struct Pose {
+    double R[9], o[3], v[3], w[3];  // R row-major
+};
+
+// Rigid placement of sample s (the sample update of Alg. 2 (c)): x = o + R X
+// by place_coord (FP64, one rounding per operation, then FP32); u_b = R ub + v
+// + w x (x - o) with the FP32 x.  A coordinate outside the domain is clamped
+// into it (so that the set-up after the placement stays in range whether or
+// not the host waits for the count of such samples); returns whether one was.
+__device__ __forceinline__ bool place_sample(const MarkerGeom &mg, int64_t n, int64_t s, const Pose &P,
+                                             const float *__restrict__ bx, const float *__restrict__ bu,
+                                             float *__restrict__ wx, float *__restrict__ wu, float (&x)[3])
+{
+#pragma clang fp contract(off)
+    const double X[3] = {(double)bx[s], (double)bx[n + s], (double)bx[2 * n + s]};
+    const double U[3] = {(double)bu[s], (double)bu[n + s], (double)bu[2 * n + s]};
+    double r[3], ru[3];
+    bool out = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float pf = place_coord(P.R, P.o, a, X[0], X[1], X[2]);
+        const float top = domain_top(mg, a);
+        if (!(pf >= 0.0f) || !(pf < top)) {
+            out = true;
+            pf = top > 0.0f ? fminf(fmaxf(pf, 0.0f), __int_as_float(__float_as_int(top) - 1)) : 0.0f;
+        }
+        x[a] = pf;
+        wx[a * n + s] = pf;
+        r[a] = (double)pf - P.o[a];
+        ru[a] = (P.R[3 * a] * U[0] + P.R[3 * a + 1] * U[1]) + P.R[3 * a + 2] * U[2];
+    }
+    wu[s] = (float)(ru[0] + P.v[0] + (P.w[1] * r[2] - P.w[2] * r[1]));
+    wu[n + s] = (float)(ru[1] + P.v[1] + (P.w[2] * r[0] - P.w[0] * r[2]));
+    wu[2 * n + s] = (float)(ru[2] + P.v[2] + (P.w[0] * r[1] - P.w[1] * r[0]));
+    return out;
+}
+
 // Checks, base cell and sort key of each sample (input order), and the
-// histogram of the blocks.  Also clears the base-cell bit map and the count
+// histogram of the blocks.  POSED: the sample is first placed at the pose
+// (body coordinates bx, bu in, placed wx, wu out) and counted in `bad` if it
+// had to be clamped; otherwise xyz holds the positions and a sample outside
+// the domain is counted.  Also clears the base-cell bit map and the count
 // of large buckets, which later launches fill.
+template <bool POSED>
 __global__ void k_mk_keys(MarkerGeom mg, int64_t n, const float *__restrict__ xyz, unsigned long long *__restrict__ keys,
                           int32_t *__restrict__ cell, int32_t *__restrict__ bcount, int *__restrict__ bad,
-                          unsigned long long *__restrict__ occ, int64_t W, int32_t *__restrict__ nbig)
+                          unsigned long long *__restrict__ occ, int64_t W, int32_t *__restrict__ nbig, const Pose P,
+                          const float *__restrict__ bx, const float *__restrict__ bu, float *__restrict__ wx,
+                          float *__restrict__ wu)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t w = s; w < W; w += (int64_t)gridDim.x * blockDim.x) occ[w] = 0ull;
     if (s == 0) *nbig = 0;
     if (s >= n) return;
+    float pos[3];
+    if constexpr (POSED) {
+        if (place_sample(mg, n, s, P, bx, bu, wx, wu, pos)) atomicAdd(bad, 1);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) pos[a] = xyz[a * n + s];
+    }
     int b[3], B[3];
     unsigned q[3];
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float p = xyz[a * n + s];
+        const float p = pos[a];
         if (!(p >= 0.0f) || !(p < domain_top(mg, a))) ok = false;
         b[a] = ok ? (int)floorf(p) : 0;
         B[a] = b[a] / ELL;
@@ -335,7 +385,7 @@ __global__ void k_bucket_rank(int64_t n, const int32_t *__restrict__ bstart, con
 // partner, so that the virtual +inf padding up to a power of two never
 // moves), one workgroup per listed bucket.  Exits at once when none is
 // listed.
-__global__ void __launch_bounds__(1024) k_bucket_big(const int32_t *__restrict__ bstart, const int32_t *__restrict__ big,
+__global__ void __launch_bounds__(256) k_bucket_big(const int32_t *__restrict__ bstart, const int32_t *__restrict__ big,
                                                      const int32_t *__restrict__ nbig,
                                                      unsigned long long *__restrict__ tkk, int32_t *__restrict__ perm)
 {
@@ -544,45 +594,6 @@ __global__ void k_body_store(int64_t n, const float *__restrict__ xyz, const flo
     }
     ba[s] = area ? area[s] : 1.0f;
     bg[s] = gain ? gain[s] : 1.0f;
-}
-
-struct Pose {
-    double R[9], o[3], v[3], w[3];  // R row-major
-};
-
-// Rigid placement (the sample update of Alg. 2 (c)): x = o + R X by
-// place_coord (FP64, one rounding per operation, then FP32); u_b = R ub + v +
-// w x (x - o) with the FP32 x.
-// A sample placed outside the domain is counted in `bad` and clamped into it,
-// so that the set-up kernels after this one stay in range whether or not the
-// host waits for the count (the pose is refused either way).
-__global__ void k_pose(MarkerGeom mg, int64_t n, const Pose P, const float *__restrict__ bx,
-                       const float *__restrict__ bu, float *__restrict__ wx, float *__restrict__ wu,
-                       int *__restrict__ bad)
-{
-#pragma clang fp contract(off)
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const double X[3] = {(double)bx[s], (double)bx[n + s], (double)bx[2 * n + s]};
-    const double U[3] = {(double)bu[s], (double)bu[n + s], (double)bu[2 * n + s]};
-    double r[3], ru[3];
-    bool out = false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        float pf = place_coord(P.R, P.o, a, X[0], X[1], X[2]);
-        const float top = domain_top(mg, a);
-        if (!(pf >= 0.0f) || !(pf < top)) {
-            out = true;
-            pf = top > 0.0f ? fminf(fmaxf(pf, 0.0f), __int_as_float(__float_as_int(top) - 1)) : 0.0f;
-        }
-        wx[a * n + s] = pf;
-        r[a] = (double)pf - P.o[a];
-        ru[a] = (P.R[3 * a] * U[0] + P.R[3 * a + 1] * U[1]) + P.R[3 * a + 2] * U[2];
-    }
-    wu[s] = (float)(ru[0] + P.v[0] + (P.w[1] * r[2] - P.w[2] * r[1]));
-    wu[n + s] = (float)(ru[1] + P.v[1] + (P.w[2] * r[0] - P.w[0] * r[2]));
-    wu[2 * n + s] = (float)(ru[2] + P.v[2] + (P.w[0] * r[1] - P.w[1] * r[0]));
-    if (out) atomicAdd(bad, 1);
 }
 
 // Body-frame bounding box of the samples (one workgroup): lo[3], hi[3], and
@@ -888,8 +899,10 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
 // of buckets above RANK_MAX, [64] body box (7 floats)
 static int *misc_bad(lbm_ctx *c, const SolidsLayout &L) { return reinterpret_cast<int *>(c->mws + L.misc); }
 
-hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area, const float *gain,
-                        bool posed, bool wait, int *bad_host)
+// pose == NULL: xyz and ub are the positions; else they are the staging
+// arrays that the key kernel fills from the body copy at the pose
+static hipError_t setup_impl(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area,
+                             const float *gain, const Pose *pose, bool wait, int *bad_host)
 {
     SolidsLayout L;
     hipError_t e = solids_layout(c, n, &L);
@@ -908,9 +921,15 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
     int32_t *counts = I32(L.misc + 16), *nbig = I32(L.misc + 32);
     hipStream_t st = c->stream;
 
-    // A placement counted its out-of-domain samples already (k_pose).
-    if (!posed) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, bad);
-    hipLaunchKernelGGL(k_mk_keys, grid_for(n), dim3(256), 0, st, mg, n, xyz, keys, cell, bcount, bad, occ, W, nbig);
+    // the count of samples outside starts at zero, except for a placement that
+    // does not wait: its count adds up until a synchronising call reads it
+    if (!pose || wait) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, bad);
+    if (pose)
+        hipLaunchKernelGGL(k_mk_keys<true>, grid_for(n), dim3(256), 0, st, mg, n, xyz, keys, cell, bcount, bad, occ, W,
+                           nbig, *pose, c->b_xyz, c->b_ub, c->w_xyz, c->w_ub);
+    else
+        hipLaunchKernelGGL(k_mk_keys<false>, grid_for(n), dim3(256), 0, st, mg, n, xyz, keys, cell, bcount, bad, occ,
+                           W, nbig, Pose{}, nullptr, nullptr, nullptr, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     *bad_host = 0;
     if (wait) {
@@ -924,7 +943,7 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scatter, grid_for(n), dim3(256), 0, st, n, keys, bstart, bcount, tb, tkk);
     hipLaunchKernelGGL(k_bucket_rank, grid_for(n), dim3(256), 0, st, n, bstart, tb, tkk, perm, big, nbig);
-    hipLaunchKernelGGL(k_bucket_big, dim3(BIG_SORT_BLOCKS), dim3(1024), 0, st, bstart, big, nbig, tkk, perm);
+    hipLaunchKernelGGL(k_bucket_big, dim3(BIG_SORT_BLOCKS), dim3(256), 0, st, bstart, big, nbig, tkk, perm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     c->m_pos = reinterpret_cast<float *>(m + L.pos);
@@ -969,6 +988,12 @@ hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub
         return hipSuccess;
     }
     return read_counts(c);
+}
+
+hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area, const float *gain,
+                        bool wait, int *bad_host)
+{
+    return setup_impl(c, n, xyz, ub, area, gain, nullptr, wait, bad_host);
 }
 
 hipError_t read_counts(lbm_ctx *c)
@@ -1036,13 +1061,7 @@ hipError_t solids_pose(lbm_ctx *c, const double R[9], const double o[3], const d
         P.v[a] = v[a];
         P.w[a] = w[a];
     }
-    const int64_t n = c->nm;
-    if (wait) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c->stream, c->dbad);
-    hipLaunchKernelGGL(k_pose, grid_for(n), dim3(256), 0, c->stream, marker_geom(c), n, P, c->b_xyz, c->b_ub, c->w_xyz,
-                       c->w_ub, c->dbad);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return solids_setup(c, n, c->w_xyz, c->w_ub, c->b_area, c->b_gain, true, wait, bad_host);
+    return setup_impl(c, c->nm, c->w_xyz, c->w_ub, c->b_area, c->b_gain, &P, wait, bad_host);
 }
 
 __global__ void k_gather_gain(int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ gain,

@@ -130,11 +130,11 @@ hipError_t launch_conserved_static(lbm_ctx *c, double out[4], int *flag);
 hipError_t launch_copy(lbm_ctx *c, void *dst, const void *src, size_t bytes);
 hipError_t launch_zero(lbm_ctx *c, void *dst, size_t bytes);
 hipError_t launch_scalar_io(lbm_ctx *c, float *dst, const float *src, bool to_state);
-// Sample set-up (keys, sort, band, slots, runs).  posed: a placement counted
-// the out-of-domain samples already; wait: read that count (and stop if it is
-// not zero) and the band and run counts back, else leave them on the device.
+// Sample set-up (keys, sort, band, slots, runs) of n samples at xyz.  wait:
+// read the count of samples outside the domain (and stop if it is not zero)
+// and the band and run counts back, else leave them on the device.
 hipError_t solids_setup(lbm_ctx *c, int64_t n, const float *xyz, const float *ub, const float *area, const float *gain,
-                        bool posed, bool wait, int *bad_count_host);
+                        bool wait, int *bad_count_host);
 hipError_t read_counts(lbm_ctx *c);
 // body-frame bounding box of the samples (box_lo, box_hi, box_state); waits
 hipError_t body_box(lbm_ctx *c);
