@@ -394,12 +394,12 @@ __global__ void __launch_bounds__(256) k_bucket_big(const int32_t *__restrict__ 
         const uint32_t b = (uint32_t)big[e];
         const int32_t lo = bstart[b], c = bstart[b + 1] - lo;
         unsigned long long *a = tkk + lo;
-        int32_t P = 1;
+        int64_t P = 1;  // 64-bit: c may exceed 2^30
         while (P < c) P <<= 1;
-        for (int32_t k = 2; k <= P; k <<= 1)
-            for (int32_t j = k >> 1; j > 0; j >>= 1) {
+        for (int64_t k = 2; k <= P; k <<= 1)
+            for (int64_t j = k >> 1; j > 0; j >>= 1) {
                 for (int32_t i = threadIdx.x; i < c; i += blockDim.x) {
-                    const int32_t l = j == (k >> 1) ? (i ^ (k - 1)) : (i ^ j);
+                    const int64_t l = j == (k >> 1) ? (i ^ (k - 1)) : (i ^ j);
                     if (l > i && l < c) {
                         const unsigned long long u = a[i], v = a[l];
                         if (u > v) {
