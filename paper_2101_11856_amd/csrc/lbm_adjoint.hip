@@ -100,11 +100,12 @@ __device__ __forceinline__ bool near_face(const Geom &g, int x, int y, int z)
 }
 
 // FP32 arithmetic forms: capped at 128 VGPRs (4 waves per SIMD instead of 3). The band variant
-// then spills 2 VGPRs, the band-free one 26; the backward step still runs 4% faster. The FP64
-// form would spill about 300 and keeps the compiler's choice.
+// then spills 2 VGPRs, the band-free one 26; the backward step still runs 4% faster. The form
+// for unit high-order rates is capped at 96 (5 waves per SIMD; 2 / 9 VGPRs spilled, backward
+// 0.205 -> 0.2035 ms/step).  The FP64 form would spill about 300 and keeps the compiler's choice.
 // UNIT: the orders 3 to 6 relax at rate 1 (the forward step's collide_unit_high).
 template <int ST, bool BAND, bool UNIT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == LBM_F64 ? 1 : 4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == LBM_F64 ? 1 : (UNIT ? 5 : 4))))
 k_adj_collide(const AdjParams<ST> P)
 {
     using R = typename Store<ST>::R;
