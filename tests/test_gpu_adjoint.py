@@ -9,6 +9,8 @@
 3. Full channel configuration (128x64x64, 2000 steps, checkpoint every 100):
    FP32 adjoint through torch.autograd against FP64 central differences of
    the GPU forward, within 1e-3 relative.
+4. Bookkeeping: interleaved forward runs keep their own gradients; a reverse
+   sweep split over several calls equals the single call.
 """
 import numpy as np
 import pytest
@@ -220,7 +222,7 @@ def test_adjoint_matches_oracle_finite_differences(small_fd, storage, gate):
     g_c = a.grad.cpu().numpy()
     g_d = dirs @ g.grad.cpu().numpy()
     e_c, e_d = rel_l2(g_c, g_c_ref), rel_l2(g_d, g_d_ref)
-    say(f"  J={float(J):.10e} rel err coeffs={e_c:.3e} gain dirs={e_d:.3e}")
+    say(f"  J={float(J.detach()):.10e} rel err coeffs={e_c:.3e} gain dirs={e_d:.3e}")
     assert e_c <= gate and e_d <= gate
 
 
@@ -345,3 +347,54 @@ def test_interleaved_forwards_keep_their_own_gradients():
                                  keep_checkpoints=False)
     with pytest.raises(RuntimeError):
         prob.run_backward(rec, 1.0, torch.zeros((3, prob.nz, prob.ny), dtype=torch.float64, device="cuda"))
+
+
+# ---------------------------------------------------------------------------
+# one reverse sweep split over several calls
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,gate", [("f64", 1e-12), ("f32", 1e-5)])
+def test_split_reverse_sweep_equals_one_call(storage, gate):
+    """K adjoint steps in one call against the same K steps in two calls of
+    K/2 (the later half of the tape first), with nothing, an adjoint_get, or
+    an adjoint_get + adjoint_set of what it returned between the calls.  The
+    reverse streaming is folded into the next step's collision, so a call
+    can end with the adjoint state not yet formed; adjoint_get must form it
+    without disturbing the sweep, and adjoint_set must hand it back exactly.
+    The adjoint state and both gradient accumulators (inlet profile, sample
+    gains) must agree with the single call; they differ only by the order of
+    the atomic additions in the face and interpolation transposes."""
+    nx, ny, nz, K = 70, 10, 9, 6
+    say(f"adjoint: {K} steps in one call vs two calls ({storage})")
+    rng = np.random.default_rng(91)
+    xyz, ub, area, gain = _scene(nx, ny, nz, 8)
+    prof = np.zeros((3, nz, ny))
+    prof[0] = 0.04 + 0.005 * rng.standard_normal((nz, ny))
+    s = gpu_solver(nx, ny, nz, 0.02, storage=storage, faces=(IN, OUT, NS, FS, P, P), inlet_profile=prof,
+                   body=(1e-5, 0, -1e-5))
+    s.set_solids(xyz, ub, area, gain)
+    s.adjoint_init()
+    s.set_populations(random_populations((nz, ny, nx), seed=92, amp=0.02))
+    tape = s.record_tape(K)
+    lam0 = torch.as_tensor(rng.standard_normal((27, nz, ny, nx)), device="cuda").to(s.real)
+
+    def sweep(between):
+        gi, gg = s.new_grad_inlet(), s.new_grad_gain()
+        s.adjoint_set(lam0)
+        if between is None:
+            s.adjoint_step(K, tape, gi, gg)
+        else:
+            s.adjoint_step(K // 2, tape[K // 2:], gi, gg)
+            if between != "nothing":
+                mid = s.adjoint_get()
+                if between == "get+set":
+                    s.adjoint_set(mid.clone())
+            s.adjoint_step(K // 2, tape[:K // 2], gi, gg)
+        return to_np(s.adjoint_get()), to_np(gi), to_np(gg)
+
+    one = sweep(None)
+    assert np.isfinite(one[0]).all() and np.abs(one[1]).sum() > 0 and np.abs(one[2]).sum() > 0
+    for between in ("nothing", "get", "get+set"):
+        got = sweep(between)
+        errs = [rel_l2(g, r) for g, r in zip(got, one)]
+        say(f"  two calls, {between} between: rel err lambda {errs[0]:.1e}, inlet {errs[1]:.1e}, gains {errs[2]:.1e}")
+        assert max(errs) <= gate, (between, errs)
