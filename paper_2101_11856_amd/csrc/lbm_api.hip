@@ -266,6 +266,10 @@ lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, voi
         // device's clamping guard and of the deferred LBM_E_INVAL)
         const char *pw = std::getenv("LBM_POSE_NO_WAIT");
         c->pose_no_wait = pw && std::strtol(pw, nullptr, 10) != 0;
+        // band pieces written by the fused kernel: by band size
+        // (band_push_on()) unless LBM_BAND_PUSH = 0 / 1 forces it
+        const char *bp = std::getenv("LBM_BAND_PUSH");
+        c->push_mode = bp ? (std::strtol(bp, nullptr, 10) != 0 ? 1 : 0) : -1;
     }
     c->ws = static_cast<char *>(workspace);
     c->ws_bytes = ws_bytes;
@@ -308,6 +312,7 @@ lbm_status lbm_init_equilibrium(lbm_ctx *c, const void *rho, const void *u)
 {
     CHECK_CTX(c);
     if (!rho || !u) return fail(c, LBM_E_INVAL, "rho and u must be non-NULL");
+    c->push_valid = false;
     HIP_TRY(c, launch_init_eq(c, rho, u), "lbm_init_equilibrium");
     return LBM_OK;
 }
@@ -316,6 +321,7 @@ lbm_status lbm_set_populations(lbm_ctx *c, const void *f)
 {
     CHECK_CTX(c);
     if (!f) return fail(c, LBM_E_INVAL, "f is NULL");
+    c->push_valid = false;
     HIP_TRY(c, launch_set_pop(c, f), "lbm_set_populations");
     return LBM_OK;
 }
@@ -494,14 +500,25 @@ lbm_status lbm_set_pose(lbm_ctx *c, const double R[9], const double o[3], const 
     return LBM_OK;
 }
 
-// one step from (fA, scA) into (fB, scB), without the swap
+// one step from (fA, scA) into (fB, scB), without the swap.  The band
+// pre-pass reads the band pieces when the fused kernel that wrote fA left them
+// for the current band; the fused kernel leaves them for the next step.
 static hipError_t one_step(lbm_ctx *c)
 {
+    const bool push = band_push_on(c);
     if (c->nm > 0) {
-        const hipError_t e = launch_band_ib(c, c->fA, c->ftot, !fused_spread(c));
+        const hipError_t e = launch_band_ib(c, c->fA, c->ftot, !fused_spread(c), push && c->push_valid);
         if (e != hipSuccess) return e;
     }
-    return launch_fused(c);
+    c->push_valid = false;
+    if (push && !c->feeds_valid) {
+        const hipError_t e = launch_push_feeds(c);
+        if (e != hipSuccess) return e;
+        c->feeds_valid = true;
+    }
+    const hipError_t e = launch_fused(c);
+    if (e == hipSuccess) c->push_valid = push;
+    return e;
 }
 
 lbm_status lbm_step(lbm_ctx *c, int32_t nsteps)
@@ -624,6 +641,7 @@ lbm_status lbm_restore(lbm_ctx *c, const void *src)
     CHECK_CTX(c);
     if (!src) return fail(c, LBM_E_INVAL, "src is NULL");
     const size_t fb = (size_t)c->g.total * c->esize;
+    c->push_valid = false;
     HIP_TRY(c, launch_copy(c, c->fA, src, fb), "lbm_restore");
     if (c->p.passive_scalar)
         HIP_TRY(c, launch_copy(c, c->scA, static_cast<const char *>(src) + fb, (size_t)c->rows * c->g.nxp * 4),

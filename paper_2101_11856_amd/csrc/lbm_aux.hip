@@ -884,6 +884,8 @@ hipError_t solids_layout(const lbm_ctx *c, int64_t n, SolidsLayout *L)
     L->run_cont = take(un + 1);
     L->run_sum = take(8 * un * 4 * c->rsize);
     L->band_src = take(8 * nbmax * 4);
+    L->band_push = take(18 * nbmax * c->rsize);
+    L->push_feeds = take(W * 4);
     L->body_xyz = take(3 * un * 4);
     L->body_ub = take(3 * un * 4);
     L->body_area = take(un * 4);
@@ -965,6 +967,10 @@ static hipError_t setup_impl(lbm_ctx *c, int64_t n, const float *xyz, const floa
     c->run_cont = reinterpret_cast<uint8_t *>(m + L.run_cont);
     c->run_sum = m + L.run_sum;
     c->band_src = I32(L.band_src);
+    c->band_push = m + L.band_push;
+    c->push_feeds = reinterpret_cast<uint32_t *>(m + L.push_feeds);
+    c->push_valid = false;  // a new band: no pieces for it yet
+    c->feeds_valid = false;
     c->nbcap = band_capacity(c, n);
     c->dcounts = counts;
     c->dbad = bad;

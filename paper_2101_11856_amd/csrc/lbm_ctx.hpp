@@ -72,6 +72,11 @@ struct lbm_ctx {
     int spread_mode = -1;          // -1: by band size (fused_spread()), 0: k_spread pass, 1: in the fused kernel
     void *run_sum = nullptr;       // [8][nm] real4: a K_d g summed over run r (r < nruns), per stencil offset d
     int32_t *band_src = nullptr;   // [8][nbcap] run feeding band node j (j < nband) through offset d, or -1
+    void *band_push = nullptr;     // [9][nbcap] real pairs: band pieces of the state in fA (band_push_on)
+    int push_mode = -1;            // -1: by band size (band_push_on()), 0: never, 1: always
+    bool push_valid = false;       // band_push holds the pieces of the state in fA for the current band
+    uint32_t *push_feeds = nullptr;// [W] rows of the band each wavefront of the fused kernel feeds
+    bool feeds_valid = false;      // push_feeds describes the current band
     // adjoint workspace (caller-owned)
     char *aws = nullptr;
     size_t aws_bytes = 0;
@@ -99,11 +104,27 @@ inline bool fused_spread(const lbm_ctx *c)
     return c->spread_mode >= 0 ? c->spread_mode == 1 : c->nband <= FUSED_SPREAD_MAX_BAND;
 }
 
+// Whether the fused kernel writes the band pieces of the state it produces,
+// for the next step's band pre-pass to read instead of pulling.  Measured on
+// MI355X (city, 7.16M band nodes): FP32 11.38 -> 10.50-11.01 ms per step (the
+// pre-pass 0.86 -> 0.17 ms, the fused kernel unchanged within noise); FP16
+// 7.42 -> 8.04 ms, since its fused kernel is bound by instruction issue rather
+// than HBM and the feeding wavefronts' extra work shows in full.  On small bands
+// the pre-pass is a few microseconds anyway.  So: FP32 and FP64 storage with
+// large bands, unless LBM_BAND_PUSH = 0 / 1 forces it.
+constexpr int64_t BAND_PUSH_MIN_BAND = int64_t(1) << 20;
+inline bool band_push_on(const lbm_ctx *c)
+{
+    if (c->nm <= 0 || !c->band_push) return false;
+    if (c->push_mode >= 0) return c->push_mode == 1;
+    return c->nband > BAND_PUSH_MIN_BAND && (c->p.storage == LBM_F32 || c->p.storage == LBM_F64);
+}
+
 // Marker workspace carve-up, shared by the size query and lbm_set_solids.
 struct SolidsLayout {
     size_t pos, ub, area, gain, slot, cell, cell2, perm, keys, tkk, tb, bcount, bstart, big, occ;
     size_t tile_mask, tile_start, tile_count, scan_tmp, scan_tmp_bytes, band_cell, band_ru, band_force, ib_part, misc;
-    size_t run_head, run_id, run_start, run_cont, run_sum, band_src;
+    size_t run_head, run_id, run_start, run_cont, run_sum, band_src, band_push, push_feeds;
     size_t body_xyz, body_ub, body_area, body_gain, world_xyz, world_ub;
     size_t total;
 };
@@ -113,9 +134,12 @@ int64_t band_capacity(const lbm_ctx *c, int64_t n);
 
 // launchers (return the first HIP error)
 hipError_t launch_fused(lbm_ctx *c);
+// the fused kernel's per-wavefront rows of the band it feeds (push_feeds)
+hipError_t launch_push_feeds(lbm_ctx *c);
 // band pull + interpolation/spreading of `state`; `spread` = also finish the
 // band forces (k_spread) rather than leave that to the fused kernel
-hipError_t launch_band_ib(lbm_ctx *c, const void *state, double *ftot, bool spread = true);
+// `pieces`: read the band pieces the last fused kernel wrote instead of pulling
+hipError_t launch_band_ib(lbm_ctx *c, const void *state, double *ftot, bool spread = true, bool pieces = false);
 hipError_t launch_init_eq(lbm_ctx *c, const void *rho, const void *u);
 hipError_t launch_set_pop(lbm_ctx *c, const void *f);
 hipError_t launch_get_pop(lbm_ctx *c, void *f);

@@ -1,11 +1,13 @@
 // lbm_step.hpp -- the per-step kernels of liblbm (Alg. 2 of the paper):
-//   k_band      (a)+(b) on the immersed-boundary band only: pull + rho, u
+//   k_band      (a)+(b) on the immersed-boundary band only: pull (or the band
+//               pieces the last fused kernel wrote) + rho, u
 //   k_ib_run    (c) interpolation and penalty force per sample; per run of
 //               samples sharing a base cell, the 8 spreading sums
 //   k_ib_total  (c) FP64 total force and torque from per-block partials, in order
 //   k_spread    (c) spreading completed: each band node gathers its run sums
 //   k_fused     (a)+(b)+(d)+(e) for every node: pull with face rules, rho and
-//               u, band force, central-moment collision, store
+//               u, band force, central-moment collision, store; optionally the
+//               band pieces of the next step
 #pragma once
 
 #include "lbm_ctx.hpp"
@@ -20,10 +22,19 @@ template <> struct R4T<double> {
     using type = double4;
 };
 
+template <typename R> struct R2T;
+template <> struct R2T<float> {
+    using type = float2;
+};
+template <> struct R2T<double> {
+    using type = double2;
+};
+
 template <int ST> struct StepParams {
     using R = typename Store<ST>::R;
     using T = typename Store<ST>::T;
     using R4 = typename R4T<R>::type;
+    using R2 = typename R2T<R>::type;
     Geom g;
     const T *__restrict__ fin;
     T *__restrict__ fout;
@@ -46,6 +57,12 @@ template <int ST> struct StepParams {
     int load32;     // interior loads by 32-bit offsets from a per-wavefront base (blocked layout)
     uint32_t span;  // bytes from a row's lowest source row that cover its 9 source rows
     float one;      // 1, as a run-time value (mixed-precision FP16 sums)
+    // band pieces [9][bstride] (pairs, see band_moments): written by the fused
+    // kernel for the next step's band pre-pass (null: not written), read by the
+    // pre-pass instead of pulling (null: it pulls)
+    R2 *__restrict__ push_out;
+    const R2 *__restrict__ push_in;
+    const uint32_t *__restrict__ push_feeds;  // [W] bit r: tile of row r fed by wavefront w holds band nodes
 };
 
 // ---------------------------------------------------------------------------
@@ -77,6 +94,178 @@ __device__ __forceinline__ void scalar_update(const StepParams<ST> &P, int x, in
     v -= uz > 0.f ? uz * (s0 - at(x, y, z - 1)) : uz * (at(x, y, z + 1) - s0);
     if (x == 0 && g.face[0] == LBM_INLET && y < P.sc_h) v = 1.f;
     if (active) P.sc_out[((int64_t)z * g.ny + y) * g.nxp + x] = v;
+}
+
+// ---------------------------------------------------------------------------
+// band pieces.  At a band node away from every face (1 <= x <= nx-2, the same
+// for y and z) every streamed value is a plain pull, and the sums of Eq. (2)
+// are taken by source row: for the row offset (dy, dz) of the populations
+// A = (+1, dy, dz), B = (0, dy, dz), C = (-1, dy, dz), whose streamed values
+// come from x-1, x, x+1 of row (y-dy, z-dz), piece 0 is (A + B) + C and piece
+// 1 is A - C (their x-momentum).  A is left out at the first node of a 64-node
+// segment and C at the last, since they come from the neighbouring segment;
+// they are added after the nine pieces.  The fused kernel of the step before
+// holds A, B and C of one source row and segment in three populations of
+// adjacent lanes, so it can form the pieces of the next step's band nodes
+// (push_band) and the pre-pass reads 18 coalesced values per node instead of
+// 27 scattered ones.  Both forms add in the same order: same bits.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool band_interior(const Geom &g, int x, int y, int z)
+{
+    return x >= 1 && x <= g.nx - 2 && y >= 1 && y <= g.ny - 2 && z >= 1 && z <= g.nz - 2;
+}
+
+template <typename R> __device__ __forceinline__ void band_piece(R A, R B, R C, int lane, R &p0, R &p1)
+{
+    const R a = lane != 0 ? A : (R)0, c = lane != SEG - 1 ? C : (R)0;
+    p0 = (a + B) + c;
+    p1 = a - c;
+}
+
+// piece of row offset (dy, dz) into the sums (piece 0 carries c_y and c_z)
+template <typename R> __device__ __forceinline__ void band_add(Macro<R> &m, R p0, R p1, int dy, int dz)
+{
+    m.drho += p0;
+    m.jx += p1;
+    if (dy) m.jy += dy > 0 ? p0 : -p0;
+    if (dz) m.jz += dz > 0 ? p0 : -p0;
+}
+
+// the value of population (cx, cy, cz) streamed to the interior node (x, y, z)
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::R band_pull(const StepParams<ST> &P, int cx, int cy, int cz, int x,
+                                                           int y, int z)
+{
+    const Geom &g = P.g;
+    const int i = pop_index(cx, cy, cz);
+    return Store<ST>::dec(ld_stream(P.fin + (int64_t)i * g.plane + row_off(g, y - cy, z - cz) + (x - cx)));
+}
+
+template <int ST>
+__device__ __forceinline__ Macro<typename Store<ST>::R> band_moments(const StepParams<ST> &P, int64_t b, int x, int y,
+                                                                     int z)
+{
+    using R = typename Store<ST>::R;
+    const int lane = x & (SEG - 1);
+    R A[9], C[9];
+    Macro<R> m{0, 0, 0, 0};
+    if (P.push_in) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const auto pp = P.push_in[r * P.bstride + b];
+            band_add(m, pp.x, pp.y, r % 3 - 1, r / 3 - 1);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < 9; ++r) A[r] = band_pull<ST>(P, 1, r % 3 - 1, r / 3 - 1, x, y, z);
+        }
+        if (lane == SEG - 1) {
+#pragma unroll
+            for (int r = 0; r < 9; ++r) C[r] = band_pull<ST>(P, -1, r % 3 - 1, r / 3 - 1, x, y, z);
+        }
+    } else {
+        R B[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            A[r] = band_pull<ST>(P, 1, r % 3 - 1, r / 3 - 1, x, y, z);
+            B[r] = band_pull<ST>(P, 0, r % 3 - 1, r / 3 - 1, x, y, z);
+            C[r] = band_pull<ST>(P, -1, r % 3 - 1, r / 3 - 1, x, y, z);
+        }
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            R p0, p1;
+            band_piece(A[r], B[r], C[r], lane, p0, p1);
+            band_add(m, p0, p1, r % 3 - 1, r / 3 - 1);
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) band_add(m, A[r], A[r], r % 3 - 1, r / 3 - 1);
+    }
+    if (lane == SEG - 1) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) band_add(m, C[r], -C[r], r % 3 - 1, r / 3 - 1);
+    }
+    return m;
+}
+
+// Tiles of the next step's band nodes that this wavefront's results feed: lane
+// r < 9 loads the band mask and first slot of this segment in row (y+dy, z+dz),
+// r = 3 (dz + 1) + dy + 1, when bit r of the wavefront's feeds word is set (else
+// 0).  Loaded when the wavefront starts, so that they have long arrived when
+// they are read, and held in three vector registers rather than 27 scalar ones
+// (the kernel's scalar registers already bound its occupancy).
+struct PushTiles {
+    uint32_t lo, hi;
+    int32_t start;
+};
+
+template <int ST>
+__device__ __forceinline__ void push_tiles(const StepParams<ST> &P, uint32_t w, uint32_t feeds, int lane, PushTiles &pt)
+{
+    const Geom &g = P.g;
+    const int dy = lane % 3 - 1, dz = lane / 3 - 1;
+    pt.lo = pt.hi = 0;
+    pt.start = 0;
+    if (lane < 9 && ((feeds >> lane) & 1u)) {
+        const int64_t t = (int64_t)w + ((int64_t)dz * g.ny + dy) * g.ntx;
+        const uint64_t m = P.tile_mask[t];
+        pt.lo = (uint32_t)m;
+        pt.hi = (uint32_t)(m >> 32);
+        pt.start = P.tile_start[t];
+    }
+}
+
+// Lane i receives lane i-1's value (BELOW) or lane i+1's (else); lane 0,
+// respectively 63, receives 0: a DPP wavefront shift by one lane.
+template <bool BELOW> __device__ __forceinline__ int lane_shift(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, BELOW ? 0x138 : 0x130, 0xf, 0xf, false);  // wave_shr:1 / wave_shl:1
+}
+template <bool BELOW> __device__ __forceinline__ float lane_shift(float v)
+{
+    return __builtin_bit_cast(float, lane_shift<BELOW>(__builtin_bit_cast(int, v)));
+}
+template <bool BELOW> __device__ __forceinline__ double lane_shift(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)lane_shift<BELOW>((int)(uint32_t)b), hi = (uint32_t)lane_shift<BELOW>((int)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The pieces of those band nodes: lanes of the nodes store their two pieces
+// at the node's band slot.  Called by all lanes of the wavefront (the shifts),
+// before the kernel's own stores, so that nothing is in flight when it waits
+// for the tiles.
+template <int ST>
+__device__ __forceinline__ void push_band(const StepParams<ST> &P, const typename Store<ST>::R (&f)[3][3][3],
+                                          uint32_t feeds, const PushTiles &pt, int lane)
+{
+    using R = typename Store<ST>::R;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        const int dy = r % 3 - 1, dz = r / 3 - 1;
+        if (!((feeds >> r) & 1u)) continue;
+        const uint64_t mask = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pt.hi, r) << 32) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)pt.lo, r);
+        // the stored values (16-bit forms round here as on store)
+        const R a = Store<ST>::dec(Store<ST>::enc(f[dz + 1][dy + 1][2]));
+        const R B = Store<ST>::dec(Store<ST>::enc(f[dz + 1][dy + 1][1]));
+        const R c = Store<ST>::dec(Store<ST>::enc(f[dz + 1][dy + 1][0]));
+        const R A = lane_shift<true>(a), C = lane_shift<false>(c);
+        R p0, p1;
+        band_piece(A, B, C, lane, p0, p1);
+        if ((mask >> lane) & 1ull) {
+            // band nodes of the tile below this lane
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            const int64_t slot = (int64_t)__builtin_amdgcn_readlane(pt.start, r) + below;
+            typename StepParams<ST>::R2 pp;
+            pp.x = p0;
+            pp.y = p1;
+            P.push_out[r * P.bstride + slot] = pp;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -113,6 +302,10 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     const int xc = active ? x : g.nx - 1;
 
     R Fx = P.body[0], Fy = P.body[1], Fz = P.body[2];
+    // rows of the next step's band that this wavefront feeds (0: none, or no pieces)
+    const uint32_t feeds = BAND && P.push_out ? P.push_feeds[w] : 0u;
+    PushTiles pt;
+    if (feeds) push_tiles<ST>(P, w, feeds, lane, pt);
     if (BAND) {
         const uint64_t mask = P.tile_mask[w];
         if (mask != 0 && ((mask >> lane) & 1ull)) {
@@ -211,6 +404,7 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     }
     collide_as<COLL>(f, Fx, Fy, Fz, P.rt, rho, ux, uy, uz);
     }
+    if (feeds) push_band<ST>(P, f, feeds, pt, lane);
     if (active) {
         if constexpr (B32 && LBM_BUF_STORES) {
             const BufRsrc rout = make_rsrc(P.fout + row_off(g, y, z), (uint32_t)(Q * g.plane * (int64_t)sizeof(T)));
@@ -252,7 +446,8 @@ __device__ __forceinline__ void band_node(const StepParams<ST> &P, const int32_t
     const int x = (int)(cell % g.nx);
     const int64_t r = cell / g.nx;
     const int y = (int)(r % g.ny), z = (int)(r / g.ny);
-    const Macro<R> m = node_moments<ST>(P.fin, x, y, z, g, P.inlet);
+    const Macro<R> m = band_interior(g, x, y, z) ? band_moments<ST>(P, b, x, y, z)
+                                                 : node_moments<ST>(P.fin, x, y, z, g, P.inlet);
     const R rho = (R)1 + m.drho, inv = (R)1 / rho;
     typename StepParams<ST>::R4 v;
     v.x = rho;
@@ -581,6 +776,9 @@ template <int ST> StepParams<ST> make_params(lbm_ctx *c)
     P.load32 = c->load32 ? 1 : 0;
     P.span = c->span32;
     P.one = 1.0f;
+    P.push_out = nullptr;
+    P.push_in = nullptr;
+    P.push_feeds = c->push_feeds;
     return P;
 }
 
@@ -601,7 +799,8 @@ template <int ST, bool B32, int COLL> static void fused_launch(lbm_ctx *c, const
 // the fused step of one storage form and one collision model
 template <int ST, int COLL> hipError_t fused_st(lbm_ctx *c)
 {
-    const StepParams<ST> P = make_params<ST>(c);
+    StepParams<ST> P = make_params<ST>(c);
+    if (band_push_on(c)) P.push_out = static_cast<typename StepParams<ST>::R2 *>(c->band_push);
     if constexpr (ST != LBM_F64) {
         if (c->buffer_path) fused_launch<ST, true, COLL>(c, P);
         else fused_launch<ST, false, COLL>(c, P);
@@ -622,12 +821,13 @@ inline unsigned band_blocks(const lbm_ctx *c)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(nb, 1 << 20));
 }
 
-template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *ftot, bool spread)
+template <int ST> hipError_t band_ib_st(lbm_ctx *c, const void *state, double *ftot, bool spread, bool pieces)
 {
     using R = typename Store<ST>::R;
     using R4 = typename StepParams<ST>::R4;
     StepParams<ST> P = make_params<ST>(c);
     P.fin = static_cast<const typename Store<ST>::T *>(state);
+    if (pieces) P.push_in = static_cast<const typename StepParams<ST>::R2 *>(c->band_push);
     const unsigned nb = band_blocks(c);
     const int64_t known = c->counts_exact ? c->nband : -1;
     if (known >= 0)

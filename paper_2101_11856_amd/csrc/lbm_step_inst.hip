@@ -12,6 +12,6 @@
 namespace lbm {
 template hipError_t fused_st<LBM_STEP_ST, LBM_STEP_COLL>(lbm_ctx *c);
 #if LBM_STEP_COLL == 0
-template hipError_t band_ib_st<LBM_STEP_ST>(lbm_ctx *c, const void *state, double *ftot, bool spread);
+template hipError_t band_ib_st<LBM_STEP_ST>(lbm_ctx *c, const void *state, double *ftot, bool spread, bool pieces);
 #endif
 }  // namespace lbm
