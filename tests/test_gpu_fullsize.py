@@ -285,3 +285,43 @@ def test_city_full_size_maps_and_sampled_nodes(storage, tol_f, tol_s):
         worst_f, worst_s = max(worst_f, e_f), max(worst_s, e_s)
         assert e_f <= tol_f and e_s <= tol_s, (picks[k], e_f, e_s)
     say(f"  {len(picks)} sampled nodes: max rel err populations {worst_f:.2e}, scalar {worst_s:.2e}")
+
+
+def test_city_full_size_band_pieces_equal_pulls(monkeypatch):
+    """The benchmark's city steps (FP32, 7.16M band nodes) read the band's
+    streamed sums from the pieces the previous step's fused kernel wrote (the
+    default above 2^20 band nodes in FP32); the first step pulls.  Three
+    full-size steps so (steps 2 and 3 on the pieces) and with the pieces off
+    (LBM_BAND_PUSH=0) must give the same bits: force and torque totals,
+    conserved totals, and the whole state (every 64-bit word summed modulo
+    2^64, and 2^18 words sampled at random)."""
+    nx, ny, nz = 1200, 250, 840
+    say("city 1200x250x840 full size: 3 steps with band pieces vs pulling, FP32, bitwise")
+    xyz, ub, area, gain = synth.city_markers(synth.city_boxes())
+    rho, u, sc0 = smooth_fields(nx, ny, nz)
+    pick = None
+    outs = []
+    for push in (None, "0"):
+        if push is None:
+            monkeypatch.delenv("LBM_BAND_PUSH", raising=False)
+        else:
+            monkeypatch.setenv("LBM_BAND_PUSH", push)
+        s = gpu_solver(nx, ny, nz, 1e-5, storage="f32", faces=(IN, OUT, NS, FS, P, P), u_in=(0.05, 0, 0),
+                       scalar=True, scalar_inlet_height=50)
+        s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+        s.set_scalar(torch.from_numpy(sc0).cuda())
+        s.set_solids(xyz, ub, area, gain)
+        s.step(3)
+        F, T, M = np.asarray(s.ib_force()), np.asarray(s.ib_torque()), np.asarray(s.conserved())
+        words = s.checkpoint().view(torch.int64)
+        if pick is None:
+            g = torch.Generator(device="cuda").manual_seed(85)
+            pick = torch.randint(0, words.numel(), (1 << 18,), device="cuda", generator=g)
+        outs.append((F, T, M, int(words.sum()), words[pick].cpu()))
+        del s, words
+        torch.cuda.empty_cache()
+    (Fa, Ta, Ma, ha, wa), (Fb, Tb, Mb, hb, wb) = outs
+    say(f"  force {Fa}, state word sum {ha:#x} / {hb:#x}")
+    assert np.array_equal(Fa, Fb) and np.array_equal(Ta, Tb) and np.array_equal(Ma, Mb)
+    assert ha == hb and torch.equal(wa, wb)
+    assert np.isfinite(Fa).all() and np.abs(Fa).sum() > 0
