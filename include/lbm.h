@@ -139,8 +139,7 @@ lbm_status lbm_workspace_size(const lbm_params *p, size_t *bytes);
  * described there), LBM_BAND_PUSH = 0 / 1 stops / forces the fused kernel
  * writing, for the next step's band nodes, their streamed sums split by
  * source row, which the band pass then reads instead of pulling 27 scattered
- * values (by default: FP32 and FP64 storage with more than 2^20 band nodes;
- * bit-identical either way).  Keep them unchanged between the two calls. */
+ * values (by default: more than 2^20 band nodes; bit-identical either way).  Keep them unchanged between the two calls. */
 lbm_status lbm_create(const lbm_params *p, void *workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out);
 
 lbm_status lbm_set_stream(lbm_ctx *ctx, void *hip_stream);

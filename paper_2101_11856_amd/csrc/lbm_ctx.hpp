@@ -106,18 +106,16 @@ inline bool fused_spread(const lbm_ctx *c)
 
 // Whether the fused kernel writes the band pieces of the state it produces,
 // for the next step's band pre-pass to read instead of pulling.  Measured on
-// MI355X (city, 7.16M band nodes): FP32 11.38 -> 10.50-11.01 ms per step (the
-// pre-pass 0.86 -> 0.17 ms, the fused kernel unchanged within noise); FP16
-// 7.42 -> 8.04 ms, since its fused kernel is bound by instruction issue rather
-// than HBM and the feeding wavefronts' extra work shows in full.  On small bands
-// the pre-pass is a few microseconds anyway.  So: FP32 and FP64 storage with
-// large bands, unless LBM_BAND_PUSH = 0 / 1 forces it.
+// MI355X (city, 7.16M band nodes, one box, three runs): FP32 10.91-10.96 ->
+// 10.44-10.48 ms per step (the pre-pass 0.86 -> 0.17 ms), FP16 7.34-7.69 ->
+// 7.12-7.34 ms.  On small bands the pre-pass is a few microseconds anyway.  So:
+// bands above 2^20 nodes, unless LBM_BAND_PUSH = 0 / 1 forces it.
 constexpr int64_t BAND_PUSH_MIN_BAND = int64_t(1) << 20;
 inline bool band_push_on(const lbm_ctx *c)
 {
     if (c->nm <= 0 || !c->band_push) return false;
     if (c->push_mode >= 0) return c->push_mode == 1;
-    return c->nband > BAND_PUSH_MIN_BAND && (c->p.storage == LBM_F32 || c->p.storage == LBM_F64);
+    return c->nband > BAND_PUSH_MIN_BAND;
 }
 
 // Marker workspace carve-up, shared by the size query and lbm_set_solids.

@@ -216,6 +216,26 @@ __device__ __forceinline__ void push_tiles(const StepParams<ST> &P, uint32_t w, 
     }
 }
 
+// The tiles read out of the lanes into scalar registers, before the kernel's
+// stores (reading them after the stores makes the compiler wait for the stores
+// too, since it cannot tell the loads' wait apart from theirs).
+struct PushRows {
+    uint64_t mask[9];
+    int32_t start[9];
+};
+__device__ __forceinline__ void push_rows(const PushTiles &pt, uint32_t feeds, PushRows &pr)
+{
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        pr.mask[r] = 0;
+        pr.start[r] = 0;
+        if (!((feeds >> r) & 1u)) continue;
+        pr.mask[r] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pt.hi, r) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane((int)pt.lo, r);
+        pr.start[r] = __builtin_amdgcn_readlane(pt.start, r);
+    }
+}
+
 // Lane i receives lane i-1's value (BELOW) or lane i+1's (else); lane 0,
 // respectively 63, receives 0: a DPP wavefront shift by one lane.
 template <bool BELOW> __device__ __forceinline__ int lane_shift(int v)
@@ -235,19 +255,19 @@ template <bool BELOW> __device__ __forceinline__ double lane_shift(double v)
 
 // The pieces of those band nodes: lanes of the nodes store their two pieces
 // at the node's band slot.  Called by all lanes of the wavefront (the shifts),
-// before the kernel's own stores, so that nothing is in flight when it waits
-// for the tiles.
+// after the kernel's own stores (issued before them, the pieces' partial-line
+// stores held up the population stores: FP16 city 7.79-8.16 ms per step
+// against 7.12-7.34 after them).
 template <int ST>
 __device__ __forceinline__ void push_band(const StepParams<ST> &P, const typename Store<ST>::R (&f)[3][3][3],
-                                          uint32_t feeds, const PushTiles &pt, int lane)
+                                          uint32_t feeds, const PushRows &pr, int lane)
 {
     using R = typename Store<ST>::R;
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
         const int dy = r % 3 - 1, dz = r / 3 - 1;
         if (!((feeds >> r) & 1u)) continue;
-        const uint64_t mask = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pt.hi, r) << 32) |
-                              (uint32_t)__builtin_amdgcn_readlane((int)pt.lo, r);
+        const uint64_t mask = pr.mask[r];
         // the stored values (16-bit forms round here as on store)
         const R a = Store<ST>::dec(Store<ST>::enc(f[dz + 1][dy + 1][2]));
         const R B = Store<ST>::dec(Store<ST>::enc(f[dz + 1][dy + 1][1]));
@@ -259,7 +279,7 @@ __device__ __forceinline__ void push_band(const StepParams<ST> &P, const typenam
             // band nodes of the tile below this lane
             const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-            const int64_t slot = (int64_t)__builtin_amdgcn_readlane(pt.start, r) + below;
+            const int64_t slot = (int64_t)pr.start[r] + below;
             typename StepParams<ST>::R2 pp;
             pp.x = p0;
             pp.y = p1;
@@ -404,7 +424,8 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
     }
     collide_as<COLL>(f, Fx, Fy, Fz, P.rt, rho, ux, uy, uz);
     }
-    if (feeds) push_band<ST>(P, f, feeds, pt, lane);
+    PushRows pr;
+    if (feeds) push_rows(pt, feeds, pr);
     if (active) {
         if constexpr (B32 && LBM_BUF_STORES) {
             const BufRsrc rout = make_rsrc(P.fout + row_off(g, y, z), (uint32_t)(Q * g.plane * (int64_t)sizeof(T)));
@@ -421,6 +442,7 @@ __global__ void __launch_bounds__(SEG *WAVES_PER_BLOCK) k_fused(const StepParams
                                             P.fout + (int64_t)i * g.plane + base);
         }
     }
+    if (feeds) push_band<ST>(P, f, feeds, pr, lane);
     if (SCALAR) scalar_update<ST>(P, xc, y, z, (float)ux, (float)uy, (float)uz, active);
     // lanes in the row's x padding (nx <= x < nxp, last segment only) store
     // zeros, so that every byte of a state this kernel writes is defined (a
